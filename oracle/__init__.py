@@ -1,0 +1,26 @@
+"""Plain, slow CPU oracle for the GCAMPS hot path.  TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (the HIP library and its
+Python binding) never imports, links or runs anything here, and this package
+imports nothing from the product path; the two share only the seeded workload
+generator (``paper_2511_06672_amd.workload``), which holds gate lists and no
+arithmetic of the method.
+
+Everything is complex128 / exact integers, written from the paper's definitions
+(GCAMPS, Harper et al., SCA/HPCAsia 2026):
+
+* ``weyl``        generalised Pauli (Weyl) strings, their products and powers (§2.3)
+* ``clifford``    qudit Clifford gates and their conjugation rules (§2.3, Table 1)
+* ``tableau``     the Z_d stabilizer tableau and operator decomposition by
+                  Gaussian elimination (§2.2, §2.3, §2.3.1)
+* ``mps``         matrix product states, QR/SVD truncation, MPO application (§2.4)
+* ``gcamps``      the GCAMPS state psi = C|MPS>: Clifford top loop, non-Clifford
+                  bottom loop with disentangling, observables (§3)
+* ``statevector`` a dense state-vector simulator used as brute-force reference (§2.1)
+* ``adjoint``     gradients of a Weyl-observable loss w.r.t. phase-gate angles
+
+Parity status of every function is listed in the design notes; functions whose
+results are fixed only by the heuristic rules chosen for the truncated regime
+(tie-break, truncation cut placement) say "parity unpinned" in their docstring.
+"""

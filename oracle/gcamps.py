@@ -1,0 +1,239 @@
+"""GCAMPS state psi = C|MPS> (§3, Fig. 1), plain FP64 reference.
+
+Top loop: a Clifford word updates only the tableau of C.
+
+Bottom loop for a diagonal phase gate U = diag(e^{i phi_j}) on site k:
+  (a) decompose U = sum_b c_b Z_k^b by solving the d x d linear system
+      sum_b c_b omega^{bj} = e^{i phi_j} (§3: the decomposition is found by a
+      linear solve; for a diagonal gate this is a DFT),
+  (b) commute through C: C^dagger U C = sum_b c_b P^b with P = C^dagger Z_k C from
+      the tableau decomposition (§2.3.1),
+  (c) apply sum_b c_b P^b to the MPS as a bond-d MPO on the support [l, r] of P and
+      compress (centre -> l, QR l..r-1, SVD r..l+1 with R-TRUNC, renormalise),
+  (d) disentangle (§3): sweeps over all n-1 bonds, alternating left-to-right and
+      right-to-left.  At each bond the two-site tensor Theta is rotated by every
+      candidate Q_c, scored by the Renyi-2 entropy of the cut between the two
+      sites, S2_c = -ln(sum |rho_c|^2 / (tr rho_c)^2), rho_c = M_c M_c^dagger with
+      M_c the (chi_l d) x (d chi_r) matrix of Q_c Theta; the selected c* is the
+      lowest index with S2_c <= min_c S2_c + tie_tol.  If c* != 0, Theta <- Q Theta
+      and C <- C Q^dagger.  Theta is then SVD-split with R-TRUNC.  Sweeping stops
+      after a sweep that keeps the identity everywhere or after max_sweeps.
+      (The paper gives the idea of reducing entanglement with two-qudit Cliffords
+      and an exhaustive search; the entropy measure, tie rule and sweep schedule are
+      the readings listed in the design notes.  Parity of the truncated regime is
+      "parity unpinned": it is fixed only by these rules.)
+
+Observables (§3): <psi|W|psi> = <MPS|C^dagger W C|MPS> by transfer matrices;
+Re<W> is the expectation of the Hermitian O = (W + W^dagger)/2.
+
+Dense amplitudes: the oracle records every Clifford it applies to C, so it can
+rebuild C as a dense product and return psi with its true global phase.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+from .clifford import word_matrix
+from .mps import MPS
+from .tableau import Tableau
+from .weyl import Weyl, omega, site_matrix, tau
+
+
+def diagonal_coefficients(d: int, phi: Sequence[float]) -> np.ndarray:
+    """c_b with diag(e^{i phi}) = sum_b c_b Z^b, by a linear solve (step (a))."""
+    V = np.array([[omega(d) ** (b * j) for b in range(d)] for j in range(d)])
+    return np.linalg.solve(V, np.exp(1j * np.asarray(phi, dtype=np.float64)))
+
+
+def renyi2(theta: np.ndarray) -> float:
+    """S2 across the middle cut of a two-site tensor (chi_l, d, d, chi_r), direct definition."""
+    cl, d, _, cr = theta.shape
+    m = theta.reshape(cl * d, d * cr)
+    rho = m @ m.conj().T if m.shape[0] <= m.shape[1] else m.conj().T @ m
+    tr = np.real(np.trace(rho))
+    return float(-np.log(np.sum(np.abs(rho) ** 2) / tr ** 2))
+
+
+def renyi2_replica(theta: np.ndarray, q: np.ndarray) -> float:
+    """Same score via the replica identity (independent formula, tests only):
+    purity * |Theta|^4 = sum_{xyzw} W_xyzw V_xyzw(Q) with
+    F_(a x),(a' y) = sum_b Theta_axb conj(Theta_a'yb),  W_xyzw = sum_{a a'} F_(ax),(a'y) F_(a'z),(aw),
+    V_xyzw = sum Q_(s1 s2),x conj(Q_(s1' s2),y) Q_(s1' t2),z conj(Q_(s1 t2),w)."""
+    cl, d, _, cr = theta.shape
+    t = theta.reshape(cl, d * d, cr)
+    F = np.einsum("axb,cyb->axcy", t, t.conj())
+    W = np.einsum("axcy,czaw->xyzw", F, F)
+    qq = q.reshape(d, d, d * d)
+    V = np.einsum("pqx,rqy,rtz,ptw->xyzw", qq, qq.conj(), qq, qq.conj())
+    nrm2 = np.real(np.sum(np.abs(theta) ** 2))
+    purity = np.real(np.sum(W * V)) / nrm2 ** 2
+    return float(-np.log(purity))
+
+
+@dataclass
+class Config:
+    chi_max: int
+    cutoff: float
+    tie_tol: float = 1e-10
+    max_sweeps: int = 2
+    auto_disentangle: bool = True
+
+
+@dataclass
+class ChoiceEntry:
+    gate: int
+    sweep: int
+    bond: int
+    choice: int
+
+
+class Gcamps:
+    def __init__(self, d: int, n: int, cfg: Config, candidates: Sequence = ()):
+        self.d, self.n, self.cfg = d, n, cfg
+        self.tab = Tableau(d, n)
+        self.mps = MPS.product_zero(d, n)
+        self.f_est = 1.0
+        self.choice_log: List[ChoiceEntry] = []
+        self.gate_count = 0
+        self.flags = 0                      # number of degenerate cuts (parity unpinned)
+        self.record: List[Tuple[str, int, tuple, tuple]] = []
+        self.candidates = list(candidates)
+        self._cand_mats = [word_matrix(d, w.gens, w.weyl) for w in self.candidates]
+        self.last_support: Tuple[int, int] = (-1, -1)
+
+    # ------------------------------------------------------------------ top loop
+    def apply_clifford(self, site: int, gens: Sequence[int], weyl: Sequence[int]):
+        self.tab.apply_word(site, gens, weyl)
+        self.record.append(("G", site, tuple(gens), tuple(weyl)))
+
+    # ------------------------------------------------------------------ bottom loop
+    def apply_phase_rotation(self, site: int, phi: Sequence[float]):
+        d, n = self.d, self.n
+        c = diagonal_coefficients(d, phi)
+        zk = Weyl(d, np.zeros(n, np.int64), np.eye(n, dtype=np.int64)[site], 0)
+        P, _, _ = self.tab.decompose(zk)
+        sup = [i for i in range(n) if P.x[i] or P.z[i]]
+        l, r = sup[0], sup[-1]
+        self.last_support = (l, r)
+        powers = [P.power(b) for b in range(d)]
+        coeff = np.array([c[b] * tau(d) ** powers[b].p for b in range(d)])
+        ops = [[site_matrix(d, int(powers[b].x[i]), int(powers[b].z[i])) for i in range(l, r + 1)]
+               for b in range(d)]
+        self.mps.move_centre(l)
+        self.mps.apply_block_mpo(l, r, ops, coeff)
+        if r > l:
+            epss, flags = self.mps.truncate_sweep_left(l, r, self.cfg.cutoff, self.cfg.chi_max)
+            for e in epss:
+                self.f_est *= (1.0 - e)
+            self.flags += sum(flags)
+        self.gate_count += 1
+        if self.cfg.auto_disentangle and self.candidates:
+            self.disentangle()
+
+    def scores(self, theta: np.ndarray) -> np.ndarray:
+        cl, d, _, cr = theta.shape
+        out = np.empty(len(self._cand_mats))
+        for c, q in enumerate(self._cand_mats):
+            th = np.einsum("xy,ayb->axb", q, theta.reshape(cl, d * d, cr)).reshape(cl, d, d, cr)
+            out[c] = renyi2(th)
+        return out
+
+    def select(self, s2: np.ndarray) -> int:
+        lim = np.min(s2) + self.cfg.tie_tol
+        return int(np.nonzero(s2 <= lim)[0][0])
+
+    def disentangle(self) -> Tuple[int, int]:
+        """Sweeps of the disentangler; returns (sweeps run, bonds changed)."""
+        n = self.n
+        sweeps, changed_total = 0, 0
+        for sweep in range(self.cfg.max_sweeps):
+            sweeps += 1
+            changed = 0
+            left_to_right = (sweep % 2 == 0)
+            bonds = range(n - 1) if left_to_right else range(n - 2, -1, -1)
+            for i in bonds:
+                self.mps.move_centre(i if left_to_right else i + 1)
+                th = self.mps.theta(i)
+                s2 = self.scores(th)
+                c = self.select(s2)
+                self.choice_log.append(ChoiceEntry(self.gate_count - 1, sweep, i, c))
+                if c != 0:
+                    w = self.candidates[c]
+                    cl, d, _, cr = th.shape
+                    th = np.einsum("xy,ayb->axb", self._cand_mats[c],
+                                   th.reshape(cl, d * d, cr)).reshape(cl, d, d, cr)
+                    self.tab.right_multiply_dagger(i, w.gens, w.weyl)
+                    self.record.append(("Q", i, tuple(w.gens), tuple(w.weyl)))
+                    changed += 1
+                eps, flagged, _ = self.mps.split(i, th, self.cfg.cutoff, self.cfg.chi_max,
+                                                 move_right=left_to_right)
+                self.f_est *= (1.0 - eps)
+                self.flags += int(flagged)
+            changed_total += changed
+            if changed == 0:
+                break
+        return sweeps, changed_total
+
+    # ------------------------------------------------------------------ observables
+    def expectation(self, x: Sequence[int], z: Sequence[int], p: int = 0) -> complex:
+        d = self.d
+        W = Weyl(d, np.asarray(x), np.asarray(z), p)
+        P, _, _ = self.tab.decompose(W)
+        ops = [site_matrix(d, int(P.x[i]), int(P.z[i])) for i in range(self.n)]
+        return complex(tau(d) ** P.p * self.mps.expectation_product(ops))
+
+    def loss_sum_z(self) -> float:
+        """Re sum_j <Z_j>, i.e. sum_j <(Z_j + Z_j^dagger)/2> (§3 observables)."""
+        tot = 0.0
+        for j in range(self.n):
+            z = np.zeros(self.n, np.int64)
+            z[j] = 1
+            tot += self.expectation(np.zeros(self.n, np.int64), z, 0).real
+        return tot
+
+    def statevector(self) -> np.ndarray:
+        """Dense psi = C|MPS> with C rebuilt from the recorded Cliffords (true phase)."""
+        d, n = self.d, self.n
+        v = self.mps.to_dense()
+        gates = [r for r in self.record if r[0] == "G"]
+        dis = [r for r in self.record if r[0] == "Q"]
+        # C = (G_last ... G_first)(Q_first^dagger ... Q_last^dagger)
+        for _, site, gens, weyl in reversed(dis):
+            v = apply_dense_two_site(v, d, n, site, word_matrix(d, gens, weyl).conj().T)
+        for _, site, gens, weyl in gates:
+            v = apply_dense_two_site(v, d, n, site, word_matrix(d, gens, weyl))
+        return v
+
+    def dense_clifford(self) -> np.ndarray:
+        """Dense matrix of C (very small n only)."""
+        d, n = self.d, self.n
+        D = d ** n
+        cols = [self._apply_C(np.eye(D, dtype=np.complex128)[:, j]) for j in range(D)]
+        return np.stack(cols, axis=1)
+
+    def _apply_C(self, v):
+        d, n = self.d, self.n
+        for _, site, gens, weyl in reversed([r for r in self.record if r[0] == "Q"]):
+            v = apply_dense_two_site(v, d, n, site, word_matrix(d, gens, weyl).conj().T)
+        for _, site, gens, weyl in [r for r in self.record if r[0] == "G"]:
+            v = apply_dense_two_site(v, d, n, site, word_matrix(d, gens, weyl))
+        return v
+
+
+def apply_dense_two_site(v: np.ndarray, d: int, n: int, site: int, u: np.ndarray) -> np.ndarray:
+    t = v.reshape(d ** site, d * d, d ** (n - site - 2))
+    return np.einsum("xy,ayb->axb", u, t).reshape(-1)
+
+
+def run_circuit(circuit, candidates, cfg: Config, record_states: bool = False) -> Gcamps:
+    """Run a workload circuit (bricks then phase gates, layer by layer)."""
+    g = Gcamps(circuit.d, circuit.n, cfg, candidates)
+    for layer in circuit.layers:
+        for b in layer.bricks:
+            g.apply_clifford(b.site, b.word.gens, b.word.weyl)
+        for ph in layer.phases:
+            g.apply_phase_rotation(ph.site, ph.phi)
+    return g

@@ -1,0 +1,192 @@
+"""Pins of the oracle GCAMPS method (§3) against brute force, closed forms and invariants."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from oracle.clifford import word_matrix
+from oracle.gcamps import Config, Gcamps, diagonal_coefficients, renyi2, renyi2_replica, run_circuit
+from oracle.statevector import simulate
+from oracle.weyl import Weyl
+from paper_2511_06672_amd.workload import (IDENTITY_WORD, SplitMix64, Word, brickwork_circuit,
+                                           candidate_words, random_word, t_gate_phases, workload)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_exact_workload_matches_statevector():
+    """qutrits, n = 8, 20 brickwork layers, 8 T gates, no truncation: every one of the
+    6561 amplitudes equals U_circuit|0^n> (true global phase, the oracle records C)."""
+    wl = workload("exact_d3_n8")
+    g = run_circuit(wl.circuit, wl.candidates, Config(chi_max=wl.chi_max, cutoff=wl.cutoff))
+    psi, ref = g.statevector(), simulate(wl.circuit)
+    assert np.max(np.abs(psi - ref)) < 1e-10
+    assert abs(g.f_est - 1.0) < 1e-12
+    assert g.tab.symplectic_ok()
+    assert any(e.choice for e in g.choice_log)          # the disentangler did act
+
+
+def test_pure_clifford_circuit_keeps_product_state():
+    c = brickwork_circuit(3, 6, 8, 0, seed=31)
+    g = run_circuit(c, candidate_words(3, 16, 31), Config(chi_max=64, cutoff=0.0))
+    assert g.mps.bond_dims() == [1] * 5
+    ref = simulate(c)
+    for j in range(6):
+        z = np.zeros(6, int)
+        z[j] = 1
+        zd = Weyl(3, np.zeros(6, int), z, 0).dense()
+        assert np.isclose(g.expectation(np.zeros(6, int), z), np.vdot(ref, zd @ ref))
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_expectations_vs_dense(d):
+    c = brickwork_circuit(d, 5, 6, 4, seed=40 + d, one_per_layer=False)
+    g = run_circuit(c, candidate_words(d, 24, 40 + d), Config(chi_max=64, cutoff=0.0))
+    ref = simulate(c)
+    rng = SplitMix64(9)
+    for _ in range(5):
+        x = np.array([rng.below(d) for _ in range(5)])
+        z = np.array([rng.below(d) for _ in range(5)])
+        W = Weyl(d, x, z, 0)
+        assert np.isclose(g.expectation(x, z), np.vdot(ref, W.dense() @ ref), atol=1e-10)
+    loss_ref = sum(np.vdot(ref, Weyl(d, np.zeros(5, int), np.eye(5, dtype=int)[j], 0).dense() @ ref).real
+                   for j in range(5))
+    assert np.isclose(g.loss_sum_z(), loss_ref, atol=1e-10)
+
+
+def test_first_t_gate_schmidt_spectrum_closed_form():
+    """With P = C^dagger Z_k C = W(delta, s, p), delta != 0, the first T gate turns |0^n> into
+    sum_b c_b' |b delta>: across a bond with delta non-zero on both sides the Schmidt values
+    are |c_b| (for the qutrit T: 0.844030, 0.449099, 0.293128)."""
+    d, n = 3, 5
+    rng = SplitMix64(123)
+    for attempt in range(20):
+        g = Gcamps(d, n, Config(chi_max=64, cutoff=0.0, auto_disentangle=False))
+        for _ in range(6):
+            w = random_word(rng, d, 20)
+            g.apply_clifford(rng.below(n - 1), w.gens, w.weyl)
+        zk = Weyl(d, np.zeros(n, int), np.eye(n, dtype=int)[2], 0)
+        P, _, _ = g.tab.decompose(zk)
+        nz = [i for i in range(n) if P.x[i]]
+        if len(nz) >= 2:
+            break
+    g.apply_phase_rotation(2, t_gate_phases(3))
+    c = diagonal_coefficients(3, t_gate_phases(3))
+    assert np.allclose(np.sort(np.abs(c))[::-1], [0.844030, 0.449099, 0.293128], atol=1e-6)
+    v = g.mps.to_dense()
+    cut = nz[0] + 1
+    sv = np.linalg.svd(v.reshape(d ** cut, -1), compute_uv=False)
+    assert np.allclose(sv[:3], np.sort(np.abs(c))[::-1])
+    assert sv[3] < 1e-12
+
+
+def test_renyi2_closed_forms_and_replica_identity():
+    d = 3
+    prod = np.zeros((1, d, d, 1), complex)
+    prod[0, 1, 2, 0] = 1
+    assert abs(renyi2(prod)) < 1e-14                                   # product state: S2 = 0
+    bell = np.zeros((1, d, d, 1), complex)
+    for j in range(d):
+        bell[0, j, j, 0] = 1 / np.sqrt(d)
+    assert np.isclose(renyi2(bell), np.log(d))                         # maximally entangled
+    rng = np.random.default_rng(0)
+    th = rng.normal(size=(2, d, d, 3)) + 1j * rng.normal(size=(2, d, d, 3))
+    for w in candidate_words(d, 6, 5):
+        q = word_matrix(d, w.gens, w.weyl)
+        rot = np.einsum("xy,ayb->axb", q, th.reshape(2, d * d, 3)).reshape(th.shape)
+        assert np.isclose(renyi2(rot), renyi2_replica(th, q))
+
+
+def test_left_local_invariance_of_scores():
+    """Purity is unchanged by a local unitary applied after Q (same coset => equal score)."""
+    d = 3
+    rng = np.random.default_rng(1)
+    th = rng.normal(size=(3, d, d, 2)) + 1j * rng.normal(size=(3, d, d, 2))
+    q = word_matrix(d, (4, 0, 5, 3, 1), (0, 0, 0, 0))
+    loc = word_matrix(d, (0, 2, 1, 3, 3, 0), (1, 2, 0, 1))            # F/P only: local
+    s1 = renyi2(np.einsum("xy,ayb->axb", q, th.reshape(3, 9, 2)).reshape(th.shape))
+    s2 = renyi2(np.einsum("xy,ayb->axb", loc @ q, th.reshape(3, 9, 2)).reshape(th.shape))
+    assert np.isclose(s1, s2, rtol=0, atol=1e-13)
+
+
+def test_disentangler_removes_clifford_entanglement():
+    """MPS = SUM (F (x) I)|00>: maximally entangled (S2 = ln d); with SUM^-1 in the set the
+    sweep chooses it, the MPS returns to a product state and psi = C|MPS> is unchanged."""
+    d, n = 3, 2
+    cands = [IDENTITY_WORD, Word((0, 2), (0, 0, 0, 0)), Word((5,), (0, 0, 0, 0))]
+    g = Gcamps(d, n, Config(chi_max=9, cutoff=0.0), cands)
+    th = np.zeros((1, d, d, 1), complex)
+    for j in range(d):
+        th[0, j, j, 0] = 1 / np.sqrt(d)
+    g.mps.split(0, th, 0.0, 9, move_right=True)
+    assert g.mps.bond_dims() == [3]
+    before = g.statevector()
+    g.gate_count = 1
+    sweeps, changed = g.disentangle()
+    assert changed == 1 and g.choice_log[0].choice == 2
+    assert g.mps.bond_dims() == [1]
+    assert np.allclose(g.statevector(), before)
+
+
+def test_sweeps_never_increase_entropy_and_keep_norm():
+    c = brickwork_circuit(3, 6, 10, 6, seed=77, one_per_layer=False)
+    cands = candidate_words(3, 64, 77)
+    g = Gcamps(3, 6, Config(chi_max=4, cutoff=1e-8), cands)
+    for layer in c.layers:
+        for b in layer.bricks:
+            g.apply_clifford(b.site, b.word.gens, b.word.weyl)
+        for ph in layer.phases:
+            g.apply_phase_rotation(ph.site, ph.phi)
+            assert np.isclose(np.linalg.norm(g.mps.to_dense()), 1.0)
+            assert 0 < g.f_est <= 1.0
+    assert max(g.mps.bond_dims()) <= 4
+
+
+def _symplectic_generators(d):
+    """4x4 matrices over Z_d of F_a, F_b, P_a, P_b, SUM acting on (x_a, z_a, x_b, z_b),
+    read off the oracle's conjugation rules applied to unit vectors."""
+    from oracle import clifford as cl
+    mats = []
+    for g in range(5):
+        m = np.zeros((4, 4), np.int64)
+        for col in range(4):
+            v = np.zeros(4, np.int64)
+            v[col] = 1
+            x = np.array([[v[0], v[2]]])
+            z = np.array([[v[1], v[3]]])
+            p = np.array([0])
+            cl._apply_gen(d, x, z, p, g, 0, 1, False)
+            m[:, col] = [x[0, 0], z[0, 0], x[0, 1], z[0, 1]]
+        mats.append(m % d)
+    return mats
+
+
+def _group_order(gens, d):
+    start = np.eye(4, dtype=np.int64)
+    seen = {start.tobytes()}
+    frontier = [start]
+    while frontier:
+        nxt = []
+        for m in frontier:
+            for g in gens:
+                h = (g @ m) % d
+                k = h.tobytes()
+                if k not in seen:
+                    seen.add(k)
+                    nxt.append(h)
+        frontier = nxt
+    return len(seen)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_coset_count_matches_paper(d):
+    """§3: there are 20 (d=2) and 90 (d=3) uniquely entangling two-qudit Cliffords:
+    |Sp(4,Z_d)| / |Sp(2,Z_d)|^2 from the generators' symplectic action."""
+    want = {int(a): int(b) for a, b in (l.split() for l in open(os.path.join(GOLDEN, "paper_counts.txt"))
+                                        if not l.startswith("#"))}
+    gens = _symplectic_generators(d)
+    full = _group_order(gens, d)
+    local = _group_order(gens[:4], d)
+    assert full == d ** 4 * (d * d - 1) * (d ** 4 - 1)
+    assert full // local == want[d]
