@@ -1,0 +1,193 @@
+/*
+ * gcamps.h -- C ABI of the MI355X GCAMPS hot-path library (libgcamps.so).
+ *
+ * GCAMPS (Harper, Nakhl, Quella, Sevior, Usman; SCA/HPCAsia 2026) represents a
+ * qudit state as psi = C|MPS>: C is a Clifford stored as a Z_d stabilizer
+ * tableau (§2.2-§2.3) and |MPS> a matrix product state (§2.4, Eq. (MPS)).
+ * Clifford gates only update the tableau (top loop of Fig. 1); a non-Clifford
+ * gate is decomposed into Weyl operators, commuted through C (§2.3.1), applied
+ * to the MPS and followed by disentangling (bottom loop of Fig. 1, §3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int32 status: GCAMPS_OK (0) or a negative code.
+ *   gcamps_last_error() gives a thread-local message for the last failure.
+ * - d must be prime (the operator decomposition of §2.3.1 solves a linear
+ *   system over the field Z_d); d <= 7 and n <= 128 are supported.
+ * - Host arrays passed in are borrowed for the duration of the call only.
+ * - Device memory: the caller allocates one device workspace of
+ *   gcamps_workspace_bytes() bytes (e.g. a torch uint8 tensor) and passes it to
+ *   gcamps_init; the library never frees it and the ctx must not outlive it.
+ *   Pinned host staging and the per-ctx candidate tables are allocated by the
+ *   library and released by gcamps_destroy / gcamps_candset_destroy.
+ * - Streams: all device work of a ctx is enqueued on the HIP stream given to
+ *   gcamps_init (e.g. torch.cuda.current_stream().cuda_stream).  Calls that
+ *   return host values synchronise that stream.
+ * - A ctx is not thread safe; distinct ctxs are independent.
+ * - Site numbering starts at 0 (site 0 is the most significant digit of a
+ *   computational-basis index).  Weyl phases are powers of tau = exp(i pi/d).
+ * - Results are deterministic: identical inputs give bit-identical outputs.
+ * - After GCAMPS_EDEVICE or GCAMPS_ENUMERIC the ctx is poisoned: only getters
+ *   and gcamps_destroy may follow.  Other failed calls leave the state as it
+ *   was.
+ */
+#ifndef GCAMPS_H
+#define GCAMPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GCAMPS_OK = 0,
+  GCAMPS_EINVAL = -1,       /* bad argument (site, size, null pointer, d, n) */
+  GCAMPS_EUNSUPPORTED = -2, /* valid request outside what is implemented (non-prime d, ...) */
+  GCAMPS_EWORKSPACE = -3,   /* workspace smaller than gcamps_workspace_bytes() */
+  GCAMPS_ECAPACITY = -4,    /* a bond or candidate count would exceed configured capacity */
+  GCAMPS_EDEVICE = -5,      /* HIP runtime error */
+  GCAMPS_ENUMERIC = -6      /* NaN/Inf or non-convergence on the device */
+};
+
+/* Precision of disentangler candidate scoring.  The committed factorisations,
+ * truncation and renormalisation are FP64 in every mode. */
+enum {
+  GCAMPS_SCORE_FP64 = 0, /* complex128 scoring */
+  GCAMPS_SCORE_FP32 = 1  /* complex64 scoring, FP64 re-score of the near-tie window */
+};
+
+typedef struct gcamps_ctx gcamps_ctx;
+typedef struct gcamps_candset gcamps_candset;
+
+typedef struct {
+  int32_t d;                /* qudit dimension, prime, 2..7 */
+  int32_t n;                /* number of sites, 2..128 */
+  int32_t chi_max;          /* maximal bond dimension kept by truncation */
+  double cutoff;            /* discarded relative weight allowed per bond (R-TRUNC) */
+  int32_t score_prec;       /* GCAMPS_SCORE_* */
+  double near_tie;          /* low-precision re-score window in S2 units (>= 1e-6) */
+  double tie_tol;           /* FP64 tie tolerance of the argmin (default 1e-10) */
+  int32_t max_sweeps;       /* disentangling sweeps per non-Clifford gate (default 2) */
+  int32_t auto_disentangle; /* 1: gcamps_apply_phase_rotation disentangles afterwards */
+  int32_t max_candidates;   /* capacity of the candidate table (>= candidate count) */
+} gcamps_config;
+
+/* A two-qudit Clifford word on the ordered pair (a, b) = (site, site + 1):
+ * U = (X^w0 Z^w1 (x) X^w2 Z^w3) G_{len-1} ... G_1 G_0 with generator codes
+ * 0 = F_a, 1 = F_b, 2 = P_a, 3 = P_b, 4 = SUM_{a->b}, 5 = SUM^{-1}_{a->b}
+ * (F = H_d, P = S_d and SUM_d as defined in §2.3; gens[0] is applied first). */
+typedef struct {
+  int32_t len;
+  const uint8_t* gens;
+  int32_t weyl[4];
+} gcamps_word;
+
+/* Bytes of device workspace a ctx with this configuration needs.
+ * Errors: EINVAL (null pointer, d/n/chi_max out of range), EUNSUPPORTED (d not prime). */
+int32_t gcamps_workspace_bytes(const gcamps_config* cfg, size_t* bytes);
+
+/* Create a state |0...0>: C = I (tableau S_k = Z_k, D_k = X_k), every MPS bond of
+ * dimension 1, fidelity estimate 1 (§3).  dev_workspace: device pointer of at
+ * least gcamps_workspace_bytes() bytes, 256-byte aligned; hip_stream: a
+ * hipStream_t (NULL = default stream).
+ * Errors: EINVAL, EUNSUPPORTED, EWORKSPACE, EDEVICE. */
+int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
+                    void* hip_stream, gcamps_ctx** out);
+
+/* Release host resources of a ctx (not the caller's workspace).  NULL is a no-op. */
+int32_t gcamps_destroy(gcamps_ctx* ctx);
+
+/* Clifford word on (site, site+1): C <- U C, a tableau update only (top loop,
+ * Table 1 rules).  Errors: EINVAL (site out of [0, n-2], bad generator code). */
+int32_t gcamps_apply_clifford(gcamps_ctx* ctx, int32_t site, const gcamps_word* word);
+
+/* Several words acting on disjoint pairs, applied as one tableau launch.  The
+ * pairs (sites[i], sites[i]+1) must be pairwise disjoint.  Errors: EINVAL. */
+int32_t gcamps_apply_clifford_layer(gcamps_ctx* ctx, const int32_t* sites,
+                                    const gcamps_word* words, int32_t count);
+
+/* Diagonal phase gate diag(e^{i phi_0}, ..., e^{i phi_{d-1}}) on `site`
+ * (bottom loop of Fig. 1, §3): U = sum_b c_b Z^b, C^dagger U C = sum_b c_b P^b
+ * with P = C^dagger Z_site C from the tableau (§2.3.1); the sum is applied to the
+ * MPS as a bond-d MPO on the support of P (§2.4) and compressed with FP64
+ * factorisations and the truncation rule (cutoff, chi_max); the state is
+ * renormalised and the fidelity estimate multiplied by (1 - discarded weight).
+ * With auto_disentangle and a candidate set attached (gcamps_set_candset) the
+ * disentangler runs afterwards.  phi: host array of d angles.
+ * Errors: EINVAL, ECAPACITY, ENUMERIC, EDEVICE. */
+int32_t gcamps_apply_phase_rotation(gcamps_ctx* ctx, int32_t site, const double* phi);
+
+/* Compile candidate disentanglers (§3: two-qudit Cliffords Q whose application
+ * to the MPS is compensated by C <- C Q^dagger).  words[0] must be the identity
+ * (len 0, zero Weyl shift).  Host object; count >= 1. Errors: EINVAL. */
+int32_t gcamps_candset_create(int32_t d, const gcamps_word* words, int32_t count,
+                              gcamps_candset** out);
+int32_t gcamps_candset_destroy(gcamps_candset* set);
+
+/* Attach a candidate set used by auto-disentangling (uploads it to the device).
+ * Errors: EINVAL (d mismatch), ECAPACITY (count > max_candidates), EDEVICE. */
+int32_t gcamps_set_candset(gcamps_ctx* ctx, const gcamps_candset* set);
+
+/* Disentangling sweeps (§3): sweep s runs over bonds 0..n-2 (s even) or n-2..0
+ * (s odd).  At each bond the two-site tensor Theta is rotated by every
+ * candidate Q_c and scored by the Renyi-2 entropy of its middle cut,
+ * S2_c = -ln(sum |rho_c|^2 / (tr rho_c)^2), rho_c = M_c M_c^dagger; the chosen
+ * c* is the lowest index with S2_c <= min S2 + tie_tol (in FP64; in FP32 mode
+ * every candidate within near_tie of the FP32 minimum is re-scored in FP64
+ * first).  If c* != 0: Theta <- Q Theta, C <- C Q^dagger.  Theta is then split
+ * with the truncation rule.  Sweeping stops after a sweep with c* = 0
+ * everywhere or after max_sweeps.  set may be NULL to use the attached set.
+ * out_sweeps / out_changed_bonds may be NULL.
+ * Errors: EINVAL, ECAPACITY, ENUMERIC, EDEVICE. */
+int32_t gcamps_disentangle(gcamps_ctx* ctx, const gcamps_candset* set, int32_t* out_sweeps,
+                           int32_t* out_changed_bonds);
+
+/* <psi| tau^p X^x Z^z |psi> (= <MPS| C^dagger W C |MPS>, §3 observables) as
+ * out[0] + i out[1].  x, z: host arrays of n exponents in [0, d).  Re<W> is the
+ * expectation of the Hermitian (W + W^dagger)/2.  Errors: EINVAL, EDEVICE. */
+int32_t gcamps_expectation(gcamps_ctx* ctx, const int8_t* x, const int8_t* z, int32_t p,
+                           double out[2]);
+
+/* Dense psi = C|MPS> into dev_out (d^n complex128, interleaved re/im, device
+ * memory), defined up to one global phase (the tableau fixes C only up to a
+ * phase).  dev_scratch: device memory of at least 2 * 16 * d^n bytes.  Only for
+ * d^n <= 2^20.  Errors: EINVAL, EUNSUPPORTED (d^n too large), EDEVICE. */
+int32_t gcamps_statevector(gcamps_ctx* ctx, void* dev_out, void* dev_scratch,
+                           size_t scratch_bytes);
+
+/* One amplitude <digits|psi> (same global-phase convention as
+ * gcamps_statevector); digits: n host values in [0, d).  d^n <= 2^20.
+ * Errors: EINVAL, EUNSUPPORTED, EDEVICE. */
+int32_t gcamps_amplitude(gcamps_ctx* ctx, const int8_t* digits, double out[2]);
+
+/* Tableau as an int32 [2n][2n+1] matrix: rows 0..n-1 = S_k = C Z_k C^dagger,
+ * rows n..2n-1 = D_k = C X_k C^dagger; columns x_0..x_{n-1} | z_0..z_{n-1} | p
+ * (phase in powers of tau, mod 2d). */
+int32_t gcamps_get_tableau(gcamps_ctx* ctx, int32_t* out);
+/* n-1 bond dimensions. */
+int32_t gcamps_get_bond_dims(gcamps_ctx* ctx, int32_t* out);
+/* Product of (1 - discarded weight) over every truncation so far. */
+int32_t gcamps_get_fidelity(gcamps_ctx* ctx, double* f_est);
+/* Disentangler choice log as int32 quadruples (gate, sweep, bond, c*).  Copies
+ * min(cap, len) quadruples into out (may be NULL with cap 0) and the total
+ * count into *len. */
+int32_t gcamps_get_choice_log(gcamps_ctx* ctx, int32_t* out, int64_t cap, int64_t* len);
+/* Site tensor `site` (chi_l, d, chi_r) as complex128 into host memory out
+ * (capacity cap complex values); dims written to dims[3]. */
+int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap, int32_t dims[3]);
+/* Statistics: [0] non-Clifford gates applied, [1] bonds scored, [2] candidates
+ * re-scored in FP64 (FP32 mode), [3] degenerate cuts flagged, [4] scoring flops
+ * (algorithmic), [5] factorisation flops (algorithmic), [6] scoring kernel time
+ * in ms (device events), [7] total time inside gcamps_* in ms (host). */
+int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[8]);
+
+/* Thread-local message for the last failed call on this thread. */
+const char* gcamps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCAMPS_H */

@@ -1,0 +1,86 @@
+// Launch wrappers of the HIP kernels (one definition per .hip translation unit).
+#pragma once
+
+#include "internal.h"
+
+namespace gc {
+
+// ------------------------------------------------------------------ tableau (kernels_tableau.hip)
+// Device tableau: tx[2n*n], tz[2n*n], tp[2n] (row r, site i at r*n + i); exponents in [0,d),
+// phases in [0,2d).
+void launch_tableau_init(hipStream_t s, int n, int* tx, int* tz, int* tp);
+void launch_tableau_layer(hipStream_t s, int n, int d, int count, const int* sites,
+                          const uint32_t* luts, int* tx, int* tz, int* tp);
+// C <- C Q^dagger for the candidate selected in st->cstar (no-op when 0).
+void launch_tableau_right_mult(hipStream_t s, int n, int d, int site, const DevStatus* st,
+                               const uint32_t* inv_luts, int* tx, int* tz, int* tp);
+// P = C^dagger W C for the target W (x, z, p) held in `target`; result in out.
+void launch_weyl_extract(hipStream_t s, int n, int d, const int* tx, const int* tz, const int* tp,
+                         const int* target, DevWeyl* out, int* err);
+
+// ------------------------------------------------------------------ dense linear algebra
+// C = alpha * op(A) op(B) (+ C if accumulate); row-major, complex128; op 0 = N, 1 = conj-transpose.
+// herm != 0: C is Hermitian (M == N): only the upper tiles are computed and mirrored.
+void launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, const z64* A, int lda,
+                  const z64* B, int ldb, z64* C, int ldc, z64 alpha, int accumulate, int herm);
+// Hermitian eigen-decomposition by two-sided Jacobi.  G (m x m, ld ldg) is destroyed (holds
+// the rotated matrix, padded to mp x mp with ld mp in the block variant); U (ld ldu) receives
+// eigenvectors, lam the eigenvalues (unsorted).  rel: relative-accuracy criterion.
+struct EigWork {
+  z64* G;      // padded m_pad x m_pad scratch
+  z64* V;      // block rotations
+  int* flags;  // device flags
+  int m_pad;
+};
+void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu, double* lam,
+                   int rel, EigWork& w, DevStatus* st, int* host_sweeps);
+void launch_rownorm2(hipStream_t s, const z64* B, int m, int k, int ldb, double* out);
+// Sort, truncation rule, pass-2 decision.  mode 0 = truncate (cutoff, chi_max), 1 = floor only.
+void launch_trunc(hipStream_t s, const double* sig2, int m, double cutoff, int chi_max, int mode,
+                  int* perm, double* sig_sorted, DevStatus* st);
+// Write the two factors (see kernels_linalg.hip for the case table).
+void launch_emit(hipStream_t s, int wide, int left_ortho, int renorm, int p, int q, int kept,
+                 const z64* U, int ldu, const z64* B, int ldb, const int* perm, const double* sig,
+                 z64* L, z64* R);
+void launch_copy(hipStream_t s, z64* dst, const z64* src, size_t count);
+void launch_fill_identity(hipStream_t s, z64* U, int m, int ld);
+
+// ------------------------------------------------------------------ MPS kernels (kernels_mps.hip)
+struct MpoCoeff {
+  z64 k[kMaxD];       // c_b tau^{phase of P^b}
+  z64 w[kMaxD];       // omega^j, j = 0..d-1
+};
+// Block-MPO site update.  kind: 0 = left end (opens the b index), 1 = interior, 2 = right end,
+// 3 = local operator (l == r).  (dx, dz): exponents of P on this site.
+void launch_mpo_site(hipStream_t s, int kind, int d, int chil, int chir, int dx, int dz,
+                     const MpoCoeff& coeff, const z64* in, z64* out);
+// Theta <- Q_{cstar} Theta in place (no-op when cstar == 0).  Theta (chil, d, d, chir).
+void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* st, const z64* qmats,
+                    z64* theta);
+// Candidate scores S2_c for the candidates cand_list[0..count) (or 0..count when cand_list is
+// null), in FP64 (prec 0) or FP32 (prec 1) arithmetic.  nlimit (nullable): device count that
+// overrides `count` (the list length is then only known on the device).  partial: scratch of
+// count * tiles doubles for the tiled path.
+void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64* theta,
+                  const z64* q64, const c32* q32, const int* cand_list, int count,
+                  const int* nlimit, double* s2, double* partial, size_t partial_cap);
+void launch_select(hipStream_t s, int count, const double* s2, double tie_tol, DevStatus* st);
+// Low-precision window: list (ascending index) of candidates with s2lp <= min + window; the
+// list length goes to st->nwindow.
+void launch_window(hipStream_t s, int count, const double* s2lp, double window, int* list,
+                   DevStatus* st);
+// FP64 rule over the window: c* = lowest listed index with s2 <= min + tie_tol.
+void launch_select_window(hipStream_t s, const int* list, const double* s2win, double tie_tol,
+                          DevStatus* st);
+// Weyl string applied to a dense vector of D = d^n amplitudes:
+//   out(y) (+)= coeff * tau^p omega^{<z, y - x>} in(y - x)
+void launch_apply_weyl_dense(hipStream_t s, int n, int d, long long D, const int* x, const int* z,
+                             int p, const z64* in, z64* out, int accumulate, z64 coeff);
+// psi(y) = sum_x m(x) tau^{p_x} omega^{<b_x, y - a_x>} s0(y - a_x) with per-x table
+// (a_x packed as base-d index, b_x as n digits, p_x).
+void launch_clifford_dense(hipStream_t s, int n, int d, long long D, const int* a_idx,
+                           const int8_t* b_dig, const int* p_x, const z64* mvec, const z64* s0,
+                           z64* out);
+void launch_scale(hipStream_t s, z64* v, size_t count, z64 f);
+void launch_norm2(hipStream_t s, const z64* v, size_t count, double* out);
+}  // namespace gc

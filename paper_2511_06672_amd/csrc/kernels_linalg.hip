@@ -1,0 +1,787 @@
+// Dense FP64 complex linear algebra for the MPS factorisations (§2.4: truncation by SVD).
+//
+// * k_zgemm: C = alpha op(A) op(B) on 64x64 tiles with v_mfma_f64_16x16x4 (a complex product
+//   is four real MFMAs into a real and an imaginary accumulator).
+// * Hermitian eigen-decomposition by two-sided Jacobi rotations: a single-workgroup kernel that
+//   keeps the whole matrix in LDS (m <= kSmallEig) and a block-Jacobi scheme for larger m
+//   (pairs of 32-blocks solved in LDS, the rotations applied to the matrix and the eigenvector
+//   accumulator as 64x64 MFMA tile products).
+// * k_trunc: descending sort of squared singular values and the truncation rule.
+// * k_emit: writes the two factors of a split in the requested orientation.
+#include <cfloat>
+
+#include "kernels.h"
+
+namespace gc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+// ===================================================================================== GEMM
+constexpr int TM = 64, TK = 16, LPAD = 68;
+
+template <int OPA, int OPB>
+__global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* __restrict__ A, int lda,
+                                               const z64* __restrict__ B, int ldb, z64* __restrict__ C,
+                                               int ldc, z64 alpha, int accumulate, int herm) {
+  const int tm = blockIdx.y, tn = blockIdx.x;
+  if (herm && tm > tn) return;
+  const int m0 = tm * TM, n0 = tn * TM;
+  __shared__ double As[2][TK][LPAD];
+  __shared__ double Bs[2][TK][LPAD];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  d4 accr[2][2], acci[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      accr[i][j] = (d4){0, 0, 0, 0};
+      acci[i][j] = (d4){0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < K; k0 += TK) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int e = t + 256 * i;
+      int row, kk;
+      if (OPA == 0) {
+        row = e >> 4;
+        kk = e & 15;
+      } else {
+        row = e & 63;
+        kk = e >> 6;
+      }
+      int gr = m0 + row, gk = k0 + kk;
+      z64 v = {0.0, 0.0};
+      if (gr < M && gk < K) {
+        if (OPA == 0)
+          v = A[(size_t)gr * lda + gk];
+        else {
+          v = A[(size_t)gk * lda + gr];
+          v.im = -v.im;
+        }
+      }
+      As[0][kk][row] = v.re;
+      As[1][kk][row] = v.im;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int e = t + 256 * i;
+      int col, kk;
+      if (OPB == 0) {
+        col = e & 63;
+        kk = e >> 6;
+      } else {
+        col = e >> 4;
+        kk = e & 15;
+      }
+      int gcn = n0 + col, gk = k0 + kk;
+      z64 v = {0.0, 0.0};
+      if (gcn < N && gk < K) {
+        if (OPB == 0)
+          v = B[(size_t)gk * ldb + gcn];
+        else {
+          v = B[(size_t)gcn * ldb + gk];
+          v.im = -v.im;
+        }
+      }
+      Bs[0][kk][col] = v.re;
+      Bs[1][kk][col] = v.im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const int ka = kk + (lane >> 4);
+      double ar[2], ai[2], br[2], bi[2];
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As[0][ka][wr + i * 16 + (lane & 15)];
+        ai[i] = As[1][ka][wr + i * 16 + (lane & 15)];
+        br[i] = Bs[0][ka][wc + i * 16 + (lane & 15)];
+        bi[i] = Bs[1][ka][wc + i * 16 + (lane & 15)];
+      }
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
+          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], accr[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acci[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int q = 0; q < 4; ++q) {
+        int row = m0 + wr + i * 16 + 4 * (lane >> 4) + q;
+        int col = n0 + wc + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          z64 v = {alpha.re * accr[i][j][q] - alpha.im * acci[i][j][q],
+                   alpha.re * acci[i][j][q] + alpha.im * accr[i][j][q]};
+          if (accumulate) v = cadd(v, C[(size_t)row * ldc + col]);
+          C[(size_t)row * ldc + col] = v;
+          if (herm && tm < tn) C[(size_t)col * ldc + row] = cconj(v);
+        }
+      }
+}
+
+// ===================================================================================== Jacobi
+// Round-robin (circle) pairing: step s of mp-1 steps pairs positions k and mp-1-k; position 0
+// is fixed, position i >= 1 holds element ((i - 1 + s) mod (mp - 1)) + 1.
+__device__ __forceinline__ void rr_pair(int k, int s, int mp, int& p, int& q) {
+  int i0 = k, i1 = mp - 1 - k;
+  int e0 = (i0 == 0) ? 0 : ((i0 - 1 + s) % (mp - 1)) + 1;
+  int e1 = ((i1 - 1 + s) % (mp - 1)) + 1;
+  p = e0 < e1 ? e0 : e1;
+  q = e0 < e1 ? e1 : e0;
+}
+
+// Rotation for the Hermitian 2x2 [[a, g], [conj g, b]]: J = [[c, s], [-s conj(ph), c conj(ph)]]
+// with ph = g/|g| zeroes the off-diagonal; new diagonal a - t|g|, b + t|g|.
+struct Rot {
+  double c, s;
+  z64 ph;
+  double na, nb;
+};
+
+__device__ __forceinline__ bool make_rot(double a, double b, z64 g, double thr_abs, double tol_rel,
+                                         double skip_below, int rel, Rot& r) {
+  double h = sqrt(cabs2(g));
+  bool doit;
+  if (rel)
+    doit = (h > tol_rel * sqrt(fabs(a) * fabs(b))) && (fmax(fabs(a), fabs(b)) > skip_below) && h > 0.0;
+  else
+    doit = h > thr_abs;
+  if (!doit) return false;
+  double zeta = (b - a) / (2.0 * h);
+  double t;
+  if (fabs(zeta) > 1e150)
+    t = 0.5 / zeta;
+  else
+    t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  r.c = 1.0 / sqrt(1.0 + t * t);
+  r.s = r.c * t;
+  r.ph = {g.re / h, g.im / h};
+  r.na = a - t * h;
+  r.nb = b + t * h;
+  return true;
+}
+
+// rows (p,q) <- J^H rows: row_p' = c row_p - s ph row_q ; row_q' = s row_p + c ph row_q
+__device__ __forceinline__ void rot_rows(const Rot& r, z64& xp, z64& xq) {
+  z64 a = xp, b = xq;
+  z64 phb = cmul(r.ph, b);
+  xp = csub(cscale(a, r.c), cscale(phb, r.s));
+  xq = cadd(cscale(a, r.s), cscale(phb, r.c));
+}
+// cols (p,q) <- cols J: col_p' = c col_p - s conj(ph) col_q ; col_q' = s col_p + c conj(ph) col_q
+__device__ __forceinline__ void rot_cols(const Rot& r, z64& xp, z64& xq) {
+  z64 a = xp, b = xq;
+  z64 phb = cmulc(r.ph, b);
+  xp = csub(cscale(a, r.c), cscale(phb, r.s));
+  xq = cadd(cscale(a, r.s), cscale(phb, r.c));
+}
+
+// One cyclic sweep (mp - 1 parallel steps) on an mp x mp Hermitian matrix g in LDS (ld = ldg),
+// accumulating the rotations into V (global or LDS, ld = ldv, `vrows` rows).  Returns through
+// *any whether a rotation happened.
+__device__ void jacobi_sweep_lds(z64* g, int ldg, int mp, z64* V, int ldv, int vrows, int vcols_valid,
+                                 Rot* rots, int* rflag, double thr_abs, double tol_rel, double skip_below,
+                                 int rel, int* any) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int half = mp / 2;
+  for (int step = 0; step < mp - 1; ++step) {
+    for (int k = t; k < half; k += nt) {
+      int p, q;
+      rr_pair(k, step, mp, p, q);
+      Rot r;
+      bool ok = make_rot(g[p * ldg + p].re, g[q * ldg + q].re, g[p * ldg + q], thr_abs, tol_rel, skip_below,
+                         rel, r);
+      rflag[k] = ok ? 1 : 0;
+      if (ok) {
+        rots[k] = r;
+        *any = 1;
+      }
+    }
+    __syncthreads();
+    // 2x2 blocks of the two-sided update
+    for (int idx = t; idx < half * half; idx += nt) {
+      int k1 = idx / half, k2 = idx % half;
+      int f1 = rflag[k1], f2 = rflag[k2];
+      if (!f1 && !f2) continue;
+      int p1, q1, p2, q2;
+      rr_pair(k1, step, mp, p1, q1);
+      rr_pair(k2, step, mp, p2, q2);
+      z64 b00 = g[p1 * ldg + p2], b01 = g[p1 * ldg + q2], b10 = g[q1 * ldg + p2], b11 = g[q1 * ldg + q2];
+      if (f1) {
+        rot_rows(rots[k1], b00, b10);
+        rot_rows(rots[k1], b01, b11);
+      }
+      if (f2) {
+        rot_cols(rots[k2], b00, b01);
+        rot_cols(rots[k2], b10, b11);
+      }
+      if (k1 == k2) {
+        b00 = {rots[k1].na, 0.0};
+        b11 = {rots[k1].nb, 0.0};
+        b01 = {0.0, 0.0};
+        b10 = {0.0, 0.0};
+      }
+      g[p1 * ldg + p2] = b00;
+      g[p1 * ldg + q2] = b01;
+      g[q1 * ldg + p2] = b10;
+      g[q1 * ldg + q2] = b11;
+    }
+    // eigenvector columns
+    for (int idx = t; idx < vrows * half; idx += nt) {
+      int row = idx / half, k = idx % half;
+      if (!rflag[k]) continue;
+      int p, q;
+      rr_pair(k, step, mp, p, q);
+      if (q >= vcols_valid) continue;
+      z64 xp = V[(size_t)row * ldv + p], xq = V[(size_t)row * ldv + q];
+      rot_cols(rots[k], xp, xq);
+      V[(size_t)row * ldv + p] = xp;
+      V[(size_t)row * ldv + q] = xq;
+    }
+    __syncthreads();
+  }
+}
+
+// Single-workgroup Jacobi: G (m x m) -> U (m x m), lam (m).
+__global__ __launch_bounds__(1024) void k_jacobi_small(const z64* __restrict__ G, int ldg_in, int m,
+                                                       z64* __restrict__ U, int ldu, double* __restrict__ lam,
+                                                       int rel, double tol, double skip_rel, int max_sweeps,
+                                                       DevStatus* st) {
+  extern __shared__ double smem[];
+  const int mp = m + (m & 1);
+  z64* g = reinterpret_cast<z64*>(smem);
+  Rot* rots = reinterpret_cast<Rot*>(g + mp * mp);
+  int* rflag = reinterpret_cast<int*>(rots + mp / 2);
+  __shared__ int any;
+  __shared__ double trace;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int idx = t; idx < mp * mp; idx += nt) {
+    int i = idx / mp, j = idx % mp;
+    g[idx] = (i < m && j < m) ? G[(size_t)i * ldg_in + j] : z64{0.0, 0.0};
+  }
+  for (int idx = t; idx < m * m; idx += nt) {
+    int i = idx / m, j = idx % m;
+    U[(size_t)i * ldu + j] = (i == j) ? z64{1.0, 0.0} : z64{0.0, 0.0};
+  }
+  __syncthreads();
+  if (t == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < m; ++i) tr += fabs(g[i * mp + i].re);
+    trace = tr;
+  }
+  __syncthreads();
+  const double thr = tol * trace;
+  const double skip = skip_rel * trace;
+  int sweeps = 0;
+  bool conv = false;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    if (t == 0) any = 0;
+    __syncthreads();
+    jacobi_sweep_lds(g, mp, mp, U, ldu, m, m, rots, rflag, thr, tol, skip, rel, &any);
+    ++sweeps;
+    __syncthreads();
+    if (!any) {
+      conv = true;
+      break;
+    }
+  }
+  for (int i = t; i < m; i += nt) lam[i] = g[i * mp + i].re;
+  if (t == 0 && st) {
+    st->converged = conv ? 1 : 0;
+    st->sweeps = sweeps;
+  }
+}
+
+// ----------------------------------------------------------------------- block Jacobi
+constexpr int BJ = kBlk;      // block size
+constexpr int BJ2 = 2 * kBlk; // pair size (64)
+constexpr int SLD = BJ2 + 1;  // LDS leading dimension (plane layout)
+
+// Kernel A: pair k of step s solves its 64x64 sub-problem with `inner` sweeps and writes the
+// accumulated 64x64 rotation to V + k*64*64 (row-major), plus a rotated flag.
+__global__ __launch_bounds__(512) void k_jblock_solve(const z64* __restrict__ Gp, int mp, int nb, int step,
+                                                      int inner, double thr, double tol, double skip, int rel,
+                                                      z64* __restrict__ Vout, int* __restrict__ pair_flag,
+                                                      int* __restrict__ any_flag) {
+  extern __shared__ double smem[];
+  z64* h = reinterpret_cast<z64*>(smem);   // 64 x 64
+  z64* v = h + BJ2 * BJ2;                  // 64 x 64
+  Rot* rots = reinterpret_cast<Rot*>(v + BJ2 * BJ2);
+  int* rflag = reinterpret_cast<int*>(rots + BJ);
+  __shared__ int any;
+  const int k = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+  int I, J;
+  rr_pair(k, step, nb, I, J);
+  for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+    int i = idx / BJ2, j = idx % BJ2;
+    int gi = (i < BJ ? I * BJ + i : J * BJ + (i - BJ));
+    int gj = (j < BJ ? I * BJ + j : J * BJ + (j - BJ));
+    h[idx] = Gp[(size_t)gi * mp + gj];
+    v[idx] = (i == j) ? z64{1.0, 0.0} : z64{0.0, 0.0};
+  }
+  if (t == 0) any = 0;
+  __syncthreads();
+  for (int s = 0; s < inner; ++s) {
+    jacobi_sweep_lds(h, BJ2, BJ2, v, BJ2, BJ2, BJ2, rots, rflag, thr, tol, skip, rel, &any);
+  }
+  __syncthreads();
+  z64* vo = Vout + (size_t)k * BJ2 * BJ2;
+  for (int idx = t; idx < BJ2 * BJ2; idx += nt) vo[idx] = v[idx];
+  if (t == 0) {
+    pair_flag[k] = any;
+    if (any) atomicOr(any_flag, 1);
+  }
+}
+
+// 64x64x64 complex product on four waves: acc (per wave 32x32) += A * B where
+// A is read as a[kk][row] (planes re/im, ld SLD), B as b[kk][col].  conja/conjb conjugate.
+__device__ __forceinline__ void mm64(const double* ar_, const double* ai_, const double* br_, const double* bi_,
+                                     bool conja, d4 accr[2][2], d4 acci[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  for (int kk = 0; kk < BJ2; kk += 4) {
+    const int ka = kk + (lane >> 4);
+    double ar[2], ai[2], br[2], bi[2];
+    for (int i = 0; i < 2; ++i) {
+      ar[i] = ar_[ka * SLD + wr + i * 16 + (lane & 15)];
+      ai[i] = ai_[ka * SLD + wr + i * 16 + (lane & 15)];
+      if (conja) ai[i] = -ai[i];
+      br[i] = br_[ka * SLD + wc + i * 16 + (lane & 15)];
+      bi[i] = bi_[ka * SLD + wc + i * 16 + (lane & 15)];
+    }
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
+        accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], accr[i][j], 0, 0, 0);
+        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acci[i][j], 0, 0, 0);
+        acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
+      }
+  }
+}
+
+__device__ __forceinline__ int pair_index(int P, int i, int step, int nb) {
+  int I, J;
+  rr_pair(P, step, nb, I, J);
+  return i < BJ ? I * BJ + i : J * BJ + (i - BJ);
+}
+
+// Kernel B: tiles (P, Q) of G <- V_P^H G V_Q and row tiles of U <- U V_Q.
+__global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64* __restrict__ Up, int mp, int nb,
+                                                      int step, const z64* __restrict__ V,
+                                                      const int* __restrict__ pair_flag) {
+  extern __shared__ double smem[];
+  double* a_re = smem;
+  double* a_im = a_re + BJ2 * SLD;
+  double* b_re = a_im + BJ2 * SLD;
+  double* b_im = b_re + BJ2 * SLD;
+  const int half = nb / 2;
+  const int ngt = half * half;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  int tile = blockIdx.x;
+  d4 accr[2][2], acci[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      accr[i][j] = (d4){0, 0, 0, 0};
+      acci[i][j] = (d4){0, 0, 0, 0};
+    }
+  if (tile < ngt) {
+    const int P = tile / half, Q = tile % half;
+    const int fP = pair_flag[P], fQ = pair_flag[Q];
+    if (!fP && !fQ) return;
+    const z64* VP = V + (size_t)P * BJ2 * BJ2;
+    const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
+    // A = T^T-layout: a[kk][row] = T[row][kk] = G[rows(P)[row], cols(Q)[kk]]
+    for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+      int row = idx / BJ2, kk = idx % BJ2;
+      z64 v = Gp[(size_t)pair_index(P, row, step, nb) * mp + pair_index(Q, kk, step, nb)];
+      a_re[kk * SLD + row] = v.re;
+      a_im[kk * SLD + row] = v.im;
+      z64 q = VQ[idx];  // b[kk][col] = VQ[kk][col] with kk = row index of VQ
+      b_re[(idx / BJ2) * SLD + idx % BJ2] = q.re;
+      b_im[(idx / BJ2) * SLD + idx % BJ2] = q.im;
+    }
+    __syncthreads();
+    mm64(a_re, a_im, b_re, b_im, false, accr, acci);  // X = T V_Q
+    __syncthreads();
+    // X -> b (as b[kk][col] = X[kk][col]); V_P -> a (a[kk][row] = conj(VP[kk][row]))
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int q = 0; q < 4; ++q) {
+          int row = wr + i * 16 + 4 * (lane >> 4) + q;
+          int col = wc + j * 16 + (lane & 15);
+          b_re[row * SLD + col] = accr[i][j][q];
+          b_im[row * SLD + col] = acci[i][j][q];
+          accr[i][j][q] = 0.0;
+          acci[i][j][q] = 0.0;
+        }
+    for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+      z64 p = VP[idx];
+      a_re[(idx / BJ2) * SLD + idx % BJ2] = p.re;
+      a_im[(idx / BJ2) * SLD + idx % BJ2] = p.im;
+    }
+    __syncthreads();
+    mm64(a_re, a_im, b_re, b_im, true, accr, acci);  // Y = V_P^H X
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int q = 0; q < 4; ++q) {
+          int row = wr + i * 16 + 4 * (lane >> 4) + q;
+          int col = wc + j * 16 + (lane & 15);
+          Gp[(size_t)pair_index(P, row, step, nb) * mp + pair_index(Q, col, step, nb)] =
+              z64{accr[i][j][q], acci[i][j][q]};
+        }
+  } else {
+    tile -= ngt;
+    const int R = tile / half, Q = tile % half;
+    if (!pair_flag[Q]) return;
+    const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
+    for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+      int row = idx / BJ2, kk = idx % BJ2;
+      z64 v = Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, kk, step, nb)];
+      a_re[kk * SLD + row] = v.re;
+      a_im[kk * SLD + row] = v.im;
+      z64 q = VQ[idx];
+      b_re[(idx / BJ2) * SLD + idx % BJ2] = q.re;
+      b_im[(idx / BJ2) * SLD + idx % BJ2] = q.im;
+    }
+    __syncthreads();
+    mm64(a_re, a_im, b_re, b_im, false, accr, acci);
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int q = 0; q < 4; ++q) {
+          int row = wr + i * 16 + 4 * (lane >> 4) + q;
+          int col = wc + j * 16 + (lane & 15);
+          Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, col, step, nb)] = z64{accr[i][j][q], acci[i][j][q]};
+        }
+  }
+}
+
+__global__ void k_pad_copy(const z64* __restrict__ G, int m, int ldg, z64* __restrict__ Gp, int mp,
+                           z64* __restrict__ Up) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)mp * mp) return;
+  int i = (int)(idx / mp), j = (int)(idx % mp);
+  Gp[idx] = (i < m && j < m) ? G[(size_t)i * ldg + j] : z64{0.0, 0.0};
+  Up[idx] = (i == j) ? z64{1.0, 0.0} : z64{0.0, 0.0};
+}
+
+__global__ void k_trace(const z64* __restrict__ Gp, int m, int mp, double* out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) s += fabs(Gp[(size_t)i * mp + i].re);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_unpad(const z64* __restrict__ Gp, const z64* __restrict__ Up, int m, int mp, z64* __restrict__ U,
+                        int ldu, double* __restrict__ lam) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)m * m) return;
+  int i = (int)(idx / m), j = (int)(idx % m);
+  U[(size_t)i * ldu + j] = Up[(size_t)i * mp + j];
+  if (j == 0) lam[i] = Gp[(size_t)i * mp + i].re;
+}
+
+// ===================================================================================== misc
+__global__ void k_rownorm2(const z64* __restrict__ B, int m, int k, int ldb, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int r = blockIdx.x;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) s += cabs2(B[(size_t)r * ldb + c]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = red[0];
+}
+
+// Truncation rule on squared values sig2 (any order).  Sorted descending (ties by index).
+//   w_j = sig2_j / sum sig2;  tail[k] = sum_{j >= k} w_j  (accumulated from the smallest)
+//   k_cut = smallest k >= 1 with tail[k] <= cutoff; k_floor = #{sigma_j > 1e-13 sigma_0}
+//   k = min(k_cut, k_floor, chi_max); degeneracy guard as in the truncation rule.
+// mode 1 keeps k_floor (exact moves).  need_pass2 when a kept value is below 1e-12 sig2_0.
+constexpr int TRUNC_MAX = 4096;
+__global__ __launch_bounds__(1024) void k_trunc(const double* __restrict__ sig2, int m, double cutoff, int chi_max,
+                                                int mode, int* __restrict__ perm, double* __restrict__ sig_sorted,
+                                                DevStatus* st) {
+  __shared__ double key[TRUNC_MAX];
+  __shared__ int idx[TRUNC_MAX];
+  int P2 = 1;
+  while (P2 < m) P2 <<= 1;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int i = t; i < P2; i += nt) {
+    key[i] = (i < m) ? fmax(sig2[i], 0.0) : -1.0;
+    idx[i] = i;
+  }
+  __syncthreads();
+  // bitonic sort: descending key, ascending index on ties
+  for (int size = 2; size <= P2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = t; i < P2; i += nt) {
+        int j = i ^ stride;
+        if (j > i) {
+          bool desc = ((i & size) == 0);
+          double ki = key[i], kj = key[j];
+          int ii = idx[i], ij = idx[j];
+          bool i_before_j = (ki > kj) || (ki == kj && ii < ij);
+          bool swap = desc ? !i_before_j : i_before_j;
+          if (swap) {
+            key[i] = kj;
+            key[j] = ki;
+            idx[i] = ij;
+            idx[j] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = t; i < m; i += nt) {
+    perm[i] = idx[i];
+    sig_sorted[i] = sqrt(key[i]);
+  }
+  if (t == 0) {
+    double total = 0.0;
+    for (int i = m - 1; i >= 0; --i) total += key[i];
+    // smallest k with tail[k] <= cutoff, tails accumulated from the smallest value
+    double tails_k = 0.0;
+    int kcut = m;
+    for (int k = m - 1; k >= 1; --k) {
+      tails_k += key[k] / total;
+      if (tails_k <= cutoff) kcut = k;
+      else break;
+    }
+    const double s0 = sqrt(key[0]);
+    int kfloor = 0;
+    for (int i = 0; i < m; ++i)
+      if (sqrt(key[i]) > 1e-13 * s0) ++kfloor;
+    int k;
+    int flagged = 0;
+    if (mode == 1) {
+      k = kfloor > 0 ? kfloor : 1;
+    } else {
+      k = kcut;
+      if (kfloor < k) k = kfloor;
+      if (chi_max < k) k = chi_max;
+      if (k < 1) k = 1;
+      if (k < m) {
+        double sk = sqrt(key[k]), skm = sqrt(key[k - 1]);
+        if (sk > 1e-13 * s0 && sk >= skm * (1.0 - 1e-10)) {
+          int j = k - 1;
+          while (j > 0 && sqrt(key[j]) >= sqrt(key[j - 1]) * (1.0 - 1e-10)) --j;
+          if (j == 0)
+            flagged = 1;
+          else
+            k = j;
+        }
+      }
+    }
+    double eps = 0.0;
+    for (int i = m - 1; i >= k; --i) eps += key[i] / total;
+    st->kept = k;
+    st->eps = eps;
+    st->flagged = flagged;
+    st->need_pass2 = (key[k - 1] < 1e-12 * key[0]) ? 1 : 0;
+    st->lam_max = key[0];
+  }
+}
+
+// Factor emission.  W is the wide orientation of the split matrix M (p x q): wide = 1 when
+// W = M (p <= q, m = p, kW = q), wide = 0 when W = M^H (m = q, kW = p).  With U (m x m) the
+// eigenvectors of W W^H, B = U^H W (m x kW), perm the sorted order and sig the row norms of B:
+//   wide, left_ortho : L = U[:, perm],            R = B[perm, :] * rn
+//   wide, right_ortho: L = U[:, perm] * sig * rn, R = B[perm, :] / sig
+//   tall, left_ortho : L = B[perm, :]^H / sig,    R = sig * rn * U[:, perm]^H
+//   tall, right_ortho: L = B[perm, :]^H * rn,     R = U[:, perm]^H
+// rn = 1 / sqrt(sum_kept sig^2) when renorm, else 1.
+__global__ void k_emit(int wide, int left_ortho, int renorm, int p, int q, int kept, const z64* __restrict__ U,
+                       int ldu, const z64* __restrict__ B, int ldb, const int* __restrict__ perm,
+                       const double* __restrict__ sig, z64* __restrict__ L, z64* __restrict__ R) {
+  __shared__ double rn_s;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int j = 0; j < kept; ++j) s += sig[j] * sig[j];
+    rn_s = renorm ? 1.0 / sqrt(s) : 1.0;
+  }
+  __syncthreads();
+  const double rn = rn_s;
+  size_t nl = (size_t)p * kept, nr = (size_t)kept * q;
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < nl) {
+    int i = (int)(idx / kept), j = (int)(idx % kept);
+    int pj = perm[j];
+    z64 v;
+    if (wide) {
+      v = U[(size_t)i * ldu + pj];
+      if (!left_ortho) v = cscale(v, sig[j] * rn);
+    } else {
+      v = cconj(B[(size_t)pj * ldb + i]);
+      v = left_ortho ? cscale(v, 1.0 / sig[j]) : cscale(v, rn);
+    }
+    L[idx] = v;
+  } else if (idx < nl + nr) {
+    size_t e = idx - nl;
+    int j = (int)(e / q), c = (int)(e % q);
+    int pj = perm[j];
+    z64 v;
+    if (wide) {
+      v = B[(size_t)pj * ldb + c];
+      v = left_ortho ? cscale(v, rn) : cscale(v, 1.0 / sig[j]);
+    } else {
+      v = cconj(U[(size_t)c * ldu + pj]);
+      if (left_ortho) v = cscale(v, sig[j] * rn);
+    }
+    R[e] = v;
+  }
+}
+
+__global__ void k_copy(z64* __restrict__ dst, const z64* __restrict__ src, size_t count) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) dst[idx] = src[idx];
+}
+
+__global__ void k_fill_identity(z64* U, int m, int ld) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)m * m) return;
+  int i = (int)(idx / m), j = (int)(idx % m);
+  U[(size_t)i * ld + j] = (i == j) ? z64{1.0, 0.0} : z64{0.0, 0.0};
+}
+
+inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ===================================================================================== launchers
+void launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, const z64* A, int lda, const z64* B,
+                  int ldb, z64* C, int ldc, z64 alpha, int accumulate, int herm) {
+  if (M <= 0 || N <= 0) return;
+  dim3 grid((N + TM - 1) / TM, (M + TM - 1) / TM);
+  if (opa == 0 && opb == 0)
+    hipLaunchKernelGGL((k_zgemm<0, 0>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, alpha, accumulate,
+                       herm);
+  else if (opa == 0 && opb == 1)
+    hipLaunchKernelGGL((k_zgemm<0, 1>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, alpha, accumulate,
+                       herm);
+  else if (opa == 1 && opb == 0)
+    hipLaunchKernelGGL((k_zgemm<1, 0>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, alpha, accumulate,
+                       herm);
+  else
+    hipLaunchKernelGGL((k_zgemm<1, 1>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, alpha, accumulate,
+                       herm);
+  GC_LAUNCH_CHECK();
+}
+
+void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu, double* lam, int rel, EigWork& w,
+                   DevStatus* st, int* host_sweeps) {
+  const double tol = rel ? 1e-14 : 1e-15;
+  const double skip = rel ? 1e-34 : 0.0;
+  const int max_sweeps = 40;
+  if (m <= kSmallEig) {
+    int mp = m + (m & 1);
+    size_t lds = (size_t)mp * mp * sizeof(z64) + (size_t)(mp / 2) * (sizeof(Rot) + sizeof(int)) + 64;
+    hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(1024), lds, s, G, ldg, m, U, ldu, lam, rel, tol, skip,
+                       max_sweeps, st);
+    GC_LAUNCH_CHECK();
+    if (host_sweeps) *host_sweeps = -1;
+    return;
+  }
+  const int mp = ((m + BJ2 - 1) / BJ2) * BJ2;
+  const int nb = mp / BJ;
+  GC_CHECK(mp <= w.m_pad, GCAMPS_ECAPACITY, "eigensolver workspace too small");
+  // Gp = w.G (mp x mp), Up = U-scratch stored after Gp
+  z64* Gp = w.G;
+  z64* Up = w.G + (size_t)w.m_pad * w.m_pad;
+  hipLaunchKernelGGL(k_pad_copy, dim3(blocks_for((size_t)mp * mp, 256)), dim3(256), 0, s, G, m, ldg, Gp, mp, Up);
+  GC_LAUNCH_CHECK();
+  double* d_trace = reinterpret_cast<double*>(w.flags + 512);
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, Gp, m, mp, d_trace);
+  GC_LAUNCH_CHECK();
+  double trace = 0.0;
+  GC_HIP(hipMemcpyAsync(&trace, d_trace, sizeof(double), hipMemcpyDeviceToHost, s));
+  GC_HIP(hipStreamSynchronize(s));
+  const double thr = tol * trace, skipv = skip * trace;
+  const size_t lds_a = 2 * (size_t)BJ2 * BJ2 * sizeof(z64) + (size_t)BJ * (sizeof(Rot) + sizeof(int)) + 64;
+  const size_t lds_b = 4 * (size_t)BJ2 * SLD * sizeof(double);
+  const int half = nb / 2;
+  int sweeps = 0;
+  bool conv = false;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    GC_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
+    for (int step = 0; step < nb - 1; ++step) {
+      hipLaunchKernelGGL(k_jblock_solve, dim3(half), dim3(512), lds_a, s, Gp, mp, nb, step, 1, thr, tol, skipv, rel,
+                         w.V, w.flags + 1, w.flags);
+      GC_LAUNCH_CHECK();
+      int tiles = half * half + (mp / BJ2) * half;
+      hipLaunchKernelGGL(k_jblock_apply, dim3(tiles), dim3(256), lds_b, s, Gp, Up, mp, nb, step, w.V, w.flags + 1);
+      GC_LAUNCH_CHECK();
+    }
+    ++sweeps;
+    int any = 0;
+    GC_HIP(hipMemcpyAsync(&any, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    GC_HIP(hipStreamSynchronize(s));
+    if (!any) {
+      conv = true;
+      break;
+    }
+  }
+  hipLaunchKernelGGL(k_unpad, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gp, Up, m, mp, U, ldu, lam);
+  GC_LAUNCH_CHECK();
+  GC_CHECK(conv, GCAMPS_ENUMERIC, "block Jacobi eigensolver did not converge");
+  if (host_sweeps) *host_sweeps = sweeps;
+}
+
+void linalg_set_attributes() {
+  const int lim = 160 * 1024;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_small), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_jblock_solve), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_jblock_apply), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim);
+}
+
+void launch_rownorm2(hipStream_t s, const z64* B, int m, int k, int ldb, double* out) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_rownorm2, dim3(m), dim3(256), 0, s, B, m, k, ldb, out);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_trunc(hipStream_t s, const double* sig2, int m, double cutoff, int chi_max, int mode, int* perm,
+                  double* sig_sorted, DevStatus* st) {
+  GC_CHECK(m <= TRUNC_MAX, GCAMPS_ECAPACITY, "truncation: matrix side exceeds 4096");
+  hipLaunchKernelGGL(k_trunc, dim3(1), dim3(1024), 0, s, sig2, m, cutoff, chi_max, mode, perm, sig_sorted, st);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_emit(hipStream_t s, int wide, int left_ortho, int renorm, int p, int q, int kept, const z64* U, int ldu,
+                 const z64* B, int ldb, const int* perm, const double* sig, z64* L, z64* R) {
+  size_t total = (size_t)p * kept + (size_t)kept * q;
+  hipLaunchKernelGGL(k_emit, dim3(blocks_for(total, 256)), dim3(256), 0, s, wide, left_ortho, renorm, p, q, kept, U,
+                     ldu, B, ldb, perm, sig, L, R);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_copy(hipStream_t s, z64* dst, const z64* src, size_t count) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_copy, dim3(blocks_for(count, 256)), dim3(256), 0, s, dst, src, count);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_fill_identity(hipStream_t s, z64* U, int m, int ld) {
+  hipLaunchKernelGGL(k_fill_identity, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, U, m, ld);
+  GC_LAUNCH_CHECK();
+}
+
+}  // namespace gc

@@ -1,0 +1,614 @@
+// MPS-side kernels of the GCAMPS bottom loop (§2.4, §3):
+//  * block-MPO application of sum_b c_b P^b on the support of the commuted Weyl operator,
+//  * Theta <- Q Theta for the selected disentangler,
+//  * candidate scoring by the Renyi-2 purity of the two-site cut (FP64 or FP32), as a fused
+//    one-workgroup-per-candidate kernel for small cuts and a 64x64-tile MFMA kernel that
+//    generates the rotated rows on the fly for large cuts,
+//  * FP64 selection (lowest index within tie_tol of the minimum) and the low-precision window,
+//  * dense helpers for the validation state vector.
+#include <cfloat>
+
+#include "kernels.h"
+
+namespace gc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ===================================================================================== MPO
+// (X^a Z^c A)[al, s, be] = omega^{c (s - a)} A[al, s - a, be]   (indices mod d)
+__global__ void k_mpo_site(int kind, int d, int chil, int chir, int dx, int dz, MpoCoeff co,
+                           const z64* __restrict__ in, z64* __restrict__ out) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int ol = (kind == 1 || kind == 2) ? d * chil : chil;
+  int orr = (kind == 0 || kind == 1) ? d * chir : chir;
+  size_t total = (size_t)ol * d * orr;
+  if (idx >= total) return;
+  int col = (int)(idx % orr);
+  int s = (int)((idx / orr) % d);
+  int row = (int)(idx / ((size_t)orr * d));
+  auto term = [&](int b, int al, int be) -> z64 {
+    int a = (b * dx) % d, c = (b * dz) % d;
+    int src = (s - a + d) % d;
+    z64 v = in[((size_t)al * d + src) * chir + be];
+    return cmul(co.w[(c * src) % d], v);
+  };
+  z64 v = {0.0, 0.0};
+  if (kind == 3) {
+    for (int b = 0; b < d; ++b) v = cadd(v, cmul(co.k[b], term(b, row, col)));
+  } else if (kind == 0) {
+    int b = col / chir, be = col % chir;
+    v = cmul(co.k[b], term(b, row, be));
+  } else if (kind == 2) {
+    int b = row / chil, al = row % chil;
+    v = term(b, al, col);
+  } else {
+    int bl = row / chil, al = row % chil, br = col / chir, be = col % chir;
+    if (bl == br) v = term(bl, al, be);
+  }
+  out[idx] = v;
+}
+
+// ===================================================================================== apply Q
+__global__ void k_apply_q(int d, int chil, int chir, const DevStatus* __restrict__ st, const z64* __restrict__ qm,
+                          z64* __restrict__ theta) {
+  const int c = st->cstar;
+  if (c == 0) return;
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)chil * chir) return;
+  const int a = (int)(idx / chir), b = (int)(idx % chir);
+  const int D2 = d * d;
+  const z64* q = qm + (size_t)c * D2 * D2;
+  z64 v[kMaxD * kMaxD];
+  for (int x = 0; x < D2; ++x) v[x] = theta[((size_t)a * D2 + x) * chir + b];
+  for (int y = 0; y < D2; ++y) {
+    z64 acc = {0.0, 0.0};
+    for (int x = 0; x < D2; ++x) acc = cadd(acc, cmul(q[y * D2 + x], v[x]));
+    theta[((size_t)a * D2 + y) * chir + b] = acc;
+  }
+}
+
+// ===================================================================================== scoring
+// Element of M_c = reshape(Q_c Theta) at row (a, s1') and column (s2', b):
+//   M[(a s1'), (s2' b)] = sum_{s1 s2} Q[(s1' s2'), (s1 s2)] Theta[a, s1, s2, b]
+template <typename T>
+__device__ __forceinline__ cx<T> melem(int d, int chir, const z64* __restrict__ theta, const cx<T>* q, int a,
+                                       int s1p, int s2p, int b) {
+  const int D2 = d * d;
+  const cx<T>* qrow = q + (s1p * d + s2p) * D2;
+  const z64* th = theta + (size_t)a * D2 * chir + b;
+  cx<T> acc = {T(0), T(0)};
+  for (int x = 0; x < D2; ++x) {
+    z64 tv = th[(size_t)x * chir];
+    cx<T> t = {T(tv.re), T(tv.im)};
+    acc = cadd(acc, cmul(qrow[x], t));
+  }
+  return acc;
+}
+
+// Element (i, col) of the scored matrix N: N = M when chil*d <= d*chir (rows (a s1'), cols
+// (s2' b)), else N = M^T (rows (s2' b), cols (a s1')).  ||N N^H||_F = ||M M^H||_F.
+template <typename T>
+__device__ __forceinline__ cx<T> nelem(int d, int chil, int chir, bool rows_first, const z64* __restrict__ theta,
+                                       const cx<T>* q, int i, int col) {
+  int a, s1p, s2p, b;
+  if (rows_first) {
+    a = i / d;
+    s1p = i % d;
+    s2p = col / chir;
+    b = col % chir;
+  } else {
+    s2p = i / chir;
+    b = i % chir;
+    a = col / d;
+    s1p = col % d;
+  }
+  return melem<T>(d, chir, theta, q, a, s1p, s2p, b);
+}
+
+constexpr int SMALL_M = 96;
+constexpr int SMALL_KC = 32;
+constexpr int SMALL_THREADS = 512;
+constexpr int SMALL_PPT = (SMALL_M * (SMALL_M + 1) / 2 + SMALL_THREADS - 1) / SMALL_THREADS;
+
+template <typename T>
+__device__ __forceinline__ const cx<T>* qsel(const z64* q64, const c32* q32);
+template <>
+__device__ __forceinline__ const cx<double>* qsel<double>(const z64* q64, const c32*) {
+  return q64;
+}
+template <>
+__device__ __forceinline__ const cx<float>* qsel<float>(const z64*, const c32* q32) {
+  return q32;
+}
+
+// Deterministic block sum of one double per thread (blockDim.x a power of two <= 1024).
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SMALL_THREADS) void k_score_small(int d, int chil, int chir,
+                                                               const z64* __restrict__ theta,
+                                                               const z64* __restrict__ q64,
+                                                               const c32* __restrict__ q32,
+                                                               const int* __restrict__ list,
+                                                               const int* __restrict__ nlimit,
+                                                               double* __restrict__ s2) {
+  const int slot = blockIdx.x;
+  if (nlimit && slot >= *nlimit) return;
+  const int c = list ? list[slot] : slot;
+  const bool rows_first = chil * d <= d * chir;
+  const int m = rows_first ? chil * d : d * chir;
+  const int k = rows_first ? d * chir : chil * d;
+  const int D4 = d * d * d * d;
+  __shared__ cx<T> qs[kMaxD * kMaxD * kMaxD * kMaxD];
+  __shared__ cx<T> chunk[SMALL_M * SMALL_KC];
+  __shared__ double red[SMALL_THREADS];
+  const int t = threadIdx.x;
+  const cx<T>* qall = qsel<T>(q64, q32);
+  for (int i = t; i < D4; i += SMALL_THREADS) qs[i] = qall[(size_t)c * D4 + i];
+  const int npairs = m * (m + 1) / 2;
+  int pi[SMALL_PPT], pj[SMALL_PPT];
+  cx<T> acc[SMALL_PPT];
+  for (int u = 0; u < SMALL_PPT; ++u) {
+    int e = t + u * SMALL_THREADS;
+    pi[u] = pj[u] = -1;
+    acc[u] = {T(0), T(0)};
+    if (e < npairs) {
+      // e -> (i, j), i <= j, row-major over the upper triangle
+      int i = 0, rem = e;
+      while (rem >= m - i) {
+        rem -= m - i;
+        ++i;
+      }
+      pi[u] = i;
+      pj[u] = i + rem;
+    }
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < k; k0 += SMALL_KC) {
+    const int kc = (k - k0 < SMALL_KC) ? k - k0 : SMALL_KC;
+    for (int e = t; e < m * SMALL_KC; e += SMALL_THREADS) {
+      int i = e / SMALL_KC, kk = e % SMALL_KC;
+      chunk[e] = (kk < kc) ? nelem<T>(d, chil, chir, rows_first, theta, qs, i, k0 + kk) : cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    for (int u = 0; u < SMALL_PPT; ++u) {
+      if (pi[u] < 0) continue;
+      const cx<T>* ri = chunk + pi[u] * SMALL_KC;
+      const cx<T>* rj = chunk + pj[u] * SMALL_KC;
+      cx<T> a = acc[u];
+      for (int kk = 0; kk < kc; ++kk) {
+        cx<T> x = ri[kk], y = rj[kk];
+        a.re += x.re * y.re + x.im * y.im;
+        a.im += x.im * y.re - x.re * y.im;
+      }
+      acc[u] = a;
+    }
+    __syncthreads();
+  }
+  double pur = 0.0, tr = 0.0;
+  for (int u = 0; u < SMALL_PPT; ++u) {
+    if (pi[u] < 0) continue;
+    double a2 = (double)acc[u].re * acc[u].re + (double)acc[u].im * acc[u].im;
+    pur += (pi[u] == pj[u]) ? a2 : 2.0 * a2;
+    if (pi[u] == pj[u]) tr += (double)acc[u].re;
+  }
+  pur = block_sum(pur, red);
+  tr = block_sum(tr, red);
+  if (t == 0) s2[slot] = -log(pur / (tr * tr));
+}
+
+// ----------------------------------------------------------------------- tiled MFMA scoring
+__device__ __forceinline__ d4 mfma_t(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_t(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T>
+struct AccT;
+template <>
+struct AccT<double> {
+  typedef d4 type;
+};
+template <>
+struct AccT<float> {
+  typedef f4 type;
+};
+
+constexpr int ST = 64, SKC = 16, SPAD = 68;
+
+__device__ __forceinline__ void tile_pair(int idx, int nt, int& I, int& J) {
+  int i = 0, rem = idx;
+  while (rem >= nt - i) {
+    rem -= nt - i;
+    ++i;
+  }
+  I = i;
+  J = i + rem;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_score_tiled(int d, int chil, int chir, const z64* __restrict__ theta,
+                                                     const z64* __restrict__ q64, const c32* __restrict__ q32,
+                                                     const int* __restrict__ list, const int* __restrict__ nlimit,
+                                                     int ntp, double* __restrict__ partial) {
+  typedef typename AccT<T>::type acc_t;
+  const int slot = blockIdx.y;
+  if (nlimit && slot >= *nlimit) return;
+  const int c = list ? list[slot] : slot;
+  const bool rows_first = chil * d <= d * chir;
+  const int m = rows_first ? chil * d : d * chir;
+  const int k = rows_first ? d * chir : chil * d;
+  const int nt = (m + ST - 1) / ST;
+  int I, J;
+  tile_pair(blockIdx.x, nt, I, J);
+  const int D4 = d * d * d * d;
+  __shared__ cx<T> qs[kMaxD * kMaxD * kMaxD * kMaxD];
+  __shared__ T As[2][SKC][SPAD];
+  __shared__ T Bs[2][SKC][SPAD];
+  __shared__ double red[256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const cx<T>* qall = qsel<T>(q64, q32);
+  for (int i = t; i < D4; i += 256) qs[i] = qall[(size_t)c * D4 + i];
+  __syncthreads();
+  acc_t accr[2][2], acci[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int q = 0; q < 4; ++q) {
+        accr[i][j][q] = T(0);
+        acci[i][j][q] = T(0);
+      }
+  const int r0 = I * ST, c0 = J * ST;
+  for (int k0 = 0; k0 < k; k0 += SKC) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int e = t + 256 * u;
+      int row, kk;
+      if (rows_first) {
+        row = e >> 4;
+        kk = e & 15;
+      } else {
+        row = e & 63;
+        kk = e >> 6;
+      }
+      int col = k0 + kk;
+      cx<T> va = {T(0), T(0)}, vb = {T(0), T(0)};
+      if (col < k) {
+        if (r0 + row < m) va = nelem<T>(d, chil, chir, rows_first, theta, qs, r0 + row, col);
+        if (c0 + row < m) vb = nelem<T>(d, chil, chir, rows_first, theta, qs, c0 + row, col);
+      }
+      As[0][kk][row] = va.re;
+      As[1][kk][row] = va.im;
+      Bs[0][kk][row] = vb.re;     // B operand = conj(N[J rows])^T
+      Bs[1][kk][row] = -vb.im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < SKC; kk += 4) {
+      const int ka = kk + (lane >> 4);
+      T ar[2], ai[2], br[2], bi[2];
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As[0][ka][wr + i * 16 + (lane & 15)];
+        ai[i] = As[1][ka][wr + i * 16 + (lane & 15)];
+        br[i] = Bs[0][ka][wc + i * 16 + (lane & 15)];
+        bi[i] = Bs[1][ka][wc + i * 16 + (lane & 15)];
+      }
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          accr[i][j] = mfma_t(ar[i], br[j], accr[i][j]);
+          accr[i][j] = mfma_t(-ai[i], bi[j], accr[i][j]);
+          acci[i][j] = mfma_t(ar[i], bi[j], acci[i][j]);
+          acci[i][j] = mfma_t(ai[i], br[j], acci[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  double pur = 0.0, tr = 0.0;
+  const double wgt = (I == J) ? 1.0 : 2.0;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int q = 0; q < 4; ++q) {
+        int row = r0 + wr + i * 16 + 4 * (lane >> 4) + q;
+        int col = c0 + wc + j * 16 + (lane & 15);
+        if (row < m && col < m) {
+          double re = (double)accr[i][j][q], im = (double)acci[i][j][q];
+          pur += wgt * (re * re + im * im);
+          if (I == J && row == col) tr += re;
+        }
+      }
+  pur = block_sum(pur, red);
+  tr = block_sum(tr, red);
+  if (t == 0) {
+    partial[((size_t)slot * ntp + blockIdx.x) * 2 + 0] = pur;
+    partial[((size_t)slot * ntp + blockIdx.x) * 2 + 1] = tr;
+  }
+}
+
+__global__ void k_score_reduce(int ntp, const int* __restrict__ nlimit, int count, const double* __restrict__ partial,
+                               double* __restrict__ s2) {
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  int lim = nlimit ? *nlimit : count;
+  if (slot >= lim || slot >= count) return;
+  double pur = 0.0, tr = 0.0;
+  for (int i = 0; i < ntp; ++i) {
+    pur += partial[((size_t)slot * ntp + i) * 2 + 0];
+    tr += partial[((size_t)slot * ntp + i) * 2 + 1];
+  }
+  s2[slot] = -log(pur / (tr * tr));
+}
+
+// ===================================================================================== selection
+__global__ __launch_bounds__(1024) void k_select(int count, const double* __restrict__ s2, double tol,
+                                                 DevStatus* st) {
+  __shared__ double red[1024];
+  __shared__ int redi[1024];
+  const int t = threadIdx.x;
+  double mn = DBL_MAX;
+  for (int i = t; i < count; i += 1024) mn = fmin(mn, s2[i]);
+  red[t] = mn;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) red[t] = fmin(red[t], red[t + off]);
+    __syncthreads();
+  }
+  const double smin = red[0];
+  int best = 0x7fffffff;
+  for (int i = t; i < count; i += 1024)
+    if (s2[i] <= smin + tol && i < best) best = i;
+  redi[t] = best;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) redi[t] = min(redi[t], redi[t + off]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    st->cstar = redi[0];
+    st->s2min = smin;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_window(int count, const double* __restrict__ s2lp, double window,
+                                                 int* __restrict__ list, DevStatus* st) {
+  __shared__ double red[1024];
+  __shared__ int cnt[1024];
+  const int t = threadIdx.x;
+  double mn = DBL_MAX;
+  for (int i = t; i < count; i += 1024) mn = fmin(mn, s2lp[i]);
+  red[t] = mn;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) red[t] = fmin(red[t], red[t + off]);
+    __syncthreads();
+  }
+  const double lim = red[0] + window;
+  // contiguous ranges per thread keep the list in ascending order
+  const int per = (count + 1023) / 1024;
+  const int b0 = t * per, b1 = min(count, b0 + per);
+  int my = 0;
+  for (int i = b0; i < b1; ++i)
+    if (s2lp[i] <= lim) ++my;
+  cnt[t] = my;
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      int v = cnt[i];
+      cnt[i] = run;
+      run += v;
+    }
+    st->nwindow = run;
+    st->smin_lp = red[0];
+  }
+  __syncthreads();
+  int pos = cnt[t];
+  for (int i = b0; i < b1; ++i)
+    if (s2lp[i] <= lim) list[pos++] = i;
+}
+
+__global__ __launch_bounds__(1024) void k_select_window(const int* __restrict__ list, const double* __restrict__ s2w,
+                                                        double tol, DevStatus* st) {
+  __shared__ double red[1024];
+  __shared__ int redi[1024];
+  const int t = threadIdx.x;
+  const int nw = st->nwindow;
+  double mn = DBL_MAX;
+  for (int i = t; i < nw; i += 1024) mn = fmin(mn, s2w[i]);
+  red[t] = mn;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) red[t] = fmin(red[t], red[t + off]);
+    __syncthreads();
+  }
+  const double smin = red[0];
+  int best = 0x7fffffff;
+  for (int i = t; i < nw; i += 1024)
+    if (s2w[i] <= smin + tol && list[i] < best) best = list[i];
+  redi[t] = best;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) redi[t] = min(redi[t], redi[t + off]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    st->cstar = redi[0];
+    st->s2min = smin;
+  }
+}
+
+// ===================================================================================== dense helpers
+__device__ __forceinline__ z64 tau_pow(int p, int d) {
+  double ang = M_PI * (double)p / (double)d;
+  return z64{cos(ang), sin(ang)};
+}
+
+__global__ void k_apply_weyl_dense(int n, int d, long long D, const int* __restrict__ x, const int* __restrict__ z,
+                                   int p, const z64* __restrict__ in, z64* __restrict__ out, int accumulate,
+                                   z64 coeff) {
+  long long y = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= D) return;
+  // digits of y, site 0 most significant
+  long long rem = y, src = 0, mul = 1;
+  int ph = 0;
+  for (int i = n - 1; i >= 0; --i) {
+    int yi = (int)(rem % d);
+    rem /= d;
+    int si = (yi - x[i] + d) % d;
+    ph += z[i] * si;
+    src += si * mul;
+    mul *= d;
+  }
+  z64 f = tau_pow((p + 2 * (ph % d)) % (2 * d), d);
+  z64 v = cmul(cmul(coeff, f), in[src]);
+  out[y] = accumulate ? cadd(out[y], v) : v;
+}
+
+__global__ void k_clifford_dense(int n, int d, long long D, const int* __restrict__ a_idx,
+                                 const int8_t* __restrict__ b_dig, const int* __restrict__ p_x,
+                                 const z64* __restrict__ mvec, const z64* __restrict__ s0, z64* __restrict__ out) {
+  long long y = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= D) return;
+  int yd[32];
+  long long rem = y;
+  for (int i = n - 1; i >= 0; --i) {
+    yd[i] = (int)(rem % d);
+    rem /= d;
+  }
+  z64 acc = {0.0, 0.0};
+  for (long long xi = 0; xi < D; ++xi) {
+    z64 mv = mvec[xi];
+    if (mv.re == 0.0 && mv.im == 0.0) continue;
+    long long a = a_idx[xi];
+    const int8_t* bd = b_dig + xi * n;
+    long long src = 0, mul = 1;
+    int ph = 0;
+    for (int i = n - 1; i >= 0; --i) {
+      int ai = (int)(a % d);
+      a /= d;
+      int si = (yd[i] - ai + d) % d;
+      ph += bd[i] * si;
+      src += si * mul;
+      mul *= d;
+    }
+    z64 f = tau_pow((p_x[xi] + 2 * (ph % d)) % (2 * d), d);
+    acc = cadd(acc, cmul(mv, cmul(f, s0[src])));
+  }
+  out[y] = acc;
+}
+
+__global__ void k_scale(z64* v, size_t count, z64 f) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) v[i] = cmul(v[i], f);
+}
+
+__global__ void k_norm2(const z64* __restrict__ v, size_t count, double* out) {
+  __shared__ double red[1024];
+  double s = 0.0;
+  for (size_t i = threadIdx.x; i < count; i += 1024) s += cabs2(v[i]);
+  double r = block_sum(s, red);
+  if (threadIdx.x == 0) *out = r;
+}
+
+}  // namespace
+
+// ===================================================================================== launchers
+void launch_mpo_site(hipStream_t s, int kind, int d, int chil, int chir, int dx, int dz, const MpoCoeff& co,
+                     const z64* in, z64* out) {
+  int ol = (kind == 1 || kind == 2) ? d * chil : chil;
+  int orr = (kind == 0 || kind == 1) ? d * chir : chir;
+  size_t total = (size_t)ol * d * orr;
+  hipLaunchKernelGGL(k_mpo_site, dim3(blocks_for(total, 256)), dim3(256), 0, s, kind, d, chil, chir, dx, dz, co, in,
+                     out);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* st, const z64* qmats, z64* theta) {
+  size_t total = (size_t)chil * chir;
+  hipLaunchKernelGGL(k_apply_q, dim3(blocks_for(total, 128)), dim3(128), 0, s, d, chil, chir, st, qmats, theta);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64* theta, const z64* q64, const c32* q32,
+                  const int* list, int count, const int* nlimit, double* s2, double* partial, size_t partial_cap) {
+  if (count <= 0) return;
+  const int m = (chil * d <= d * chir) ? chil * d : d * chir;
+  if (m <= SMALL_M) {
+    if (prec == GCAMPS_SCORE_FP64)
+      hipLaunchKernelGGL(k_score_small<double>, dim3(count), dim3(SMALL_THREADS), 0, s, d, chil, chir, theta, q64,
+                         q32, list, nlimit, s2);
+    else
+      hipLaunchKernelGGL(k_score_small<float>, dim3(count), dim3(SMALL_THREADS), 0, s, d, chil, chir, theta, q64, q32,
+                         list, nlimit, s2);
+    GC_LAUNCH_CHECK();
+    return;
+  }
+  const int nt = (m + ST - 1) / ST;
+  const int ntp = nt * (nt + 1) / 2;
+  GC_CHECK((size_t)count * ntp * 2 <= partial_cap, GCAMPS_ECAPACITY, "scoring partial buffer too small");
+  dim3 grid(ntp, count);
+  if (prec == GCAMPS_SCORE_FP64)
+    hipLaunchKernelGGL(k_score_tiled<double>, grid, dim3(256), 0, s, d, chil, chir, theta, q64, q32, list, nlimit,
+                       ntp, partial);
+  else
+    hipLaunchKernelGGL(k_score_tiled<float>, grid, dim3(256), 0, s, d, chil, chir, theta, q64, q32, list, nlimit, ntp,
+                       partial);
+  GC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_score_reduce, dim3(blocks_for(count, 128)), dim3(128), 0, s, ntp, nlimit, count, partial, s2);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_select(hipStream_t s, int count, const double* s2, double tie_tol, DevStatus* st) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, count, s2, tie_tol, st);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_window(hipStream_t s, int count, const double* s2lp, double window, int* list, DevStatus* st) {
+  hipLaunchKernelGGL(k_window, dim3(1), dim3(1024), 0, s, count, s2lp, window, list, st);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_select_window(hipStream_t s, const int* list, const double* s2win, double tie_tol, DevStatus* st) {
+  hipLaunchKernelGGL(k_select_window, dim3(1), dim3(1024), 0, s, list, s2win, tie_tol, st);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_apply_weyl_dense(hipStream_t s, int n, int d, long long D, const int* x, const int* z, int p,
+                             const z64* in, z64* out, int accumulate, z64 coeff) {
+  hipLaunchKernelGGL(k_apply_weyl_dense, dim3(blocks_for((size_t)D, 256)), dim3(256), 0, s, n, d, D, x, z, p, in,
+                     out, accumulate, coeff);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_clifford_dense(hipStream_t s, int n, int d, long long D, const int* a_idx, const int8_t* b_dig,
+                           const int* p_x, const z64* mvec, const z64* s0, z64* out) {
+  hipLaunchKernelGGL(k_clifford_dense, dim3(blocks_for((size_t)D, 128)), dim3(128), 0, s, n, d, D, a_idx, b_dig, p_x,
+                     mvec, s0, out);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_scale(hipStream_t s, z64* v, size_t count, z64 f) {
+  hipLaunchKernelGGL(k_scale, dim3(blocks_for(count, 256)), dim3(256), 0, s, v, count, f);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_norm2(hipStream_t s, const z64* v, size_t count, double* out) {
+  hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, s, v, count, out);
+  GC_LAUNCH_CHECK();
+}
+
+}  // namespace gc

@@ -1,0 +1,156 @@
+// Compilation of two-qudit Clifford words (host side).
+//
+// A word acts on the ordered pair (a, b).  Its action on two-qudit Weyl operators
+// tau^p X_a^{xa} Z_a^{za} X_b^{xb} Z_b^{zb} is tabulated once per word over all
+// d^4 exponent vectors: conjugation maps (v, p) to (f(v), p + g(v)), so one
+// table entry per v holds f(v) and g(v).  The per-generator rules are those of
+// Table 1 extended to powers with exact tau-phases (§2.3):
+//   F (= H_d):   (x, z, p) -> (-z, x, p - 2xz)
+//   P (= S_d):   (x, z, p) -> (x, z + x, p + x(x-1))  (odd d),  p + x^2 (even d)
+//   X^s Z^t:     (x, z, p) -> (x, z, p + 2(t x - s z))
+//   SUM a->b:    x_b += x_a, z_a -= z_b
+// The inverse table (U^dagger W U) is the inverse permutation with negated
+// phase increments.  The dense d^2 x d^2 unitary is the ordered product of the
+// §2.3 gate matrices.
+#include <cmath>
+#include <complex>
+
+#include "internal.h"
+
+namespace gc {
+
+namespace {
+
+struct W2 {
+  int xa, za, xb, zb, p;
+};
+
+inline int md(int v, int m) {
+  v %= m;
+  return v < 0 ? v + m : v;
+}
+
+void apply_gen(int d, W2& w, int g) {
+  auto F = [&](int& x, int& z) {
+    int x0 = x, z0 = z;
+    x = md(-z0, d);
+    z = x0;
+    w.p = md(w.p - 2 * x0 * z0, 2 * d);
+  };
+  auto P = [&](int& x, int& z) {
+    z = md(z + x, d);
+    w.p = md(w.p + ((d % 2) ? x * (x - 1) : x * x), 2 * d);
+  };
+  switch (g) {
+    case 0: F(w.xa, w.za); break;
+    case 1: F(w.xb, w.zb); break;
+    case 2: P(w.xa, w.za); break;
+    case 3: P(w.xb, w.zb); break;
+    case 4:
+      w.xb = md(w.xb + w.xa, d);
+      w.za = md(w.za - w.zb, d);
+      break;
+    case 5:
+      w.xb = md(w.xb - w.xa, d);
+      w.za = md(w.za + w.zb, d);
+      break;
+    default: throw Error{GCAMPS_EINVAL, "generator code out of range"};
+  }
+}
+
+using C = std::complex<double>;
+
+std::vector<C> matmul(const std::vector<C>& a, const std::vector<C>& b, int D) {
+  std::vector<C> c(D * D, 0.0);
+  for (int i = 0; i < D; ++i)
+    for (int k = 0; k < D; ++k)
+      for (int j = 0; j < D; ++j) c[i * D + j] += a[i * D + k] * b[k * D + j];
+  return c;
+}
+
+// single-qudit matrices
+std::vector<C> mat_F(int d) {
+  std::vector<C> m(d * d);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) m[j * d + i] = std::polar(1.0 / std::sqrt((double)d), 2 * M_PI * i * j / d);
+  return m;
+}
+std::vector<C> mat_P(int d) {
+  std::vector<C> m(d * d, 0.0);
+  for (int j = 0; j < d; ++j) {
+    double ang = (d % 2) ? 2 * M_PI * (j * (j - 1) / 2) / d : M_PI * j * j / d;
+    m[j * d + j] = std::polar(1.0, ang);
+  }
+  return m;
+}
+std::vector<C> mat_XZ(int d, int x, int z) {  // X^x Z^z: |j> -> omega^{zj} |j + x>
+  std::vector<C> m(d * d, 0.0);
+  for (int j = 0; j < d; ++j) m[md(j + x, d) * d + j] = std::polar(1.0, 2 * M_PI * z * j / d);
+  return m;
+}
+std::vector<C> kron(const std::vector<C>& a, const std::vector<C>& b, int d) {
+  std::vector<C> m(d * d * d * d);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      for (int k = 0; k < d; ++k)
+        for (int l = 0; l < d; ++l) m[(i * d + k) * d * d + (j * d + l)] = a[i * d + j] * b[k * d + l];
+  return m;
+}
+std::vector<C> eye(int D) {
+  std::vector<C> m(D * D, 0.0);
+  for (int i = 0; i < D; ++i) m[i * D + i] = 1.0;
+  return m;
+}
+std::vector<C> gen_matrix(int d, int g) {
+  int D = d * d;
+  auto I = eye(d);
+  switch (g) {
+    case 0: return kron(mat_F(d), I, d);
+    case 1: return kron(I, mat_F(d), d);
+    case 2: return kron(mat_P(d), I, d);
+    case 3: return kron(I, mat_P(d), d);
+    case 4:
+    case 5: {
+      std::vector<C> m(D * D, 0.0);
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+          int out = (g == 4) ? md(i + j, d) : md(j - i, d);
+          m[(i * d + out) * D + (i * d + j)] = 1.0;
+        }
+      return m;
+    }
+  }
+  throw Error{GCAMPS_EINVAL, "generator code out of range"};
+}
+
+}  // namespace
+
+CompiledWord compile_word(int d, const gcamps_word& w) {
+  GC_CHECK(w.len >= 0 && (w.len == 0 || w.gens != nullptr), GCAMPS_EINVAL, "word: bad generator list");
+  for (int i = 0; i < w.len; ++i) GC_CHECK(w.gens[i] < 6, GCAMPS_EINVAL, "word: generator code out of range");
+  for (int i = 0; i < 4; ++i)
+    GC_CHECK(w.weyl[i] >= 0 && w.weyl[i] < d, GCAMPS_EINVAL, "word: Weyl exponent out of range");
+  const int D4 = d * d * d * d;
+  CompiledWord cw;
+  cw.fwd.assign(D4, 0);
+  cw.inv.assign(D4, 0);
+  for (int v = 0; v < D4; ++v) {
+    W2 s{v / (d * d * d), (v / (d * d)) % d, (v / d) % d, v % d, 0};
+    for (int i = 0; i < w.len; ++i) apply_gen(d, s, w.gens[i]);
+    // Weyl shift X^w0 Z^w1 on a, X^w2 Z^w3 on b, applied last
+    s.p = md(s.p + 2 * (w.weyl[1] * s.xa - w.weyl[0] * s.za), 2 * d);
+    s.p = md(s.p + 2 * (w.weyl[3] * s.xb - w.weyl[2] * s.zb), 2 * d);
+    uint32_t img = ((s.xa * d + s.za) * d + s.xb) * d + s.zb;
+    cw.fwd[v] = img | ((uint32_t)s.p << 16);
+    cw.inv[img] = (uint32_t)v | ((uint32_t)md(-s.p, 2 * d) << 16);
+  }
+  const int D = d * d;
+  std::vector<C> u = eye(D);
+  for (int i = 0; i < w.len; ++i) u = matmul(gen_matrix(d, w.gens[i]), u, D);
+  u = matmul(kron(mat_XZ(d, w.weyl[0], w.weyl[1]), mat_XZ(d, w.weyl[2], w.weyl[3]), d), u, D);
+  cw.mat.resize(D * D);
+  for (int i = 0; i < D * D; ++i) cw.mat[i] = z64{u[i].real(), u[i].imag()};
+  return cw;
+}
+
+}  // namespace gc

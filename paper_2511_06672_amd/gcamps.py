@@ -1,0 +1,273 @@
+"""ctypes binding of libgcamps (include/gcamps.h), same names as the C ABI.
+
+This module only marshals arguments: every step of the simulation runs in the
+library's HIP kernels.  PyTorch supplies the device workspace (one uint8 tensor)
+and the HIP stream.  Importing it without a built library raises: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgcamps.so")
+
+GCAMPS_OK = 0
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EWORKSPACE", -4: "ECAPACITY",
+                -5: "EDEVICE", -6: "ENUMERIC"}
+SCORE_FP64, SCORE_FP32 = 0, 1
+
+SYMBOLS = [
+    "gcamps_workspace_bytes", "gcamps_init", "gcamps_destroy", "gcamps_apply_clifford",
+    "gcamps_apply_clifford_layer", "gcamps_apply_phase_rotation", "gcamps_candset_create",
+    "gcamps_candset_destroy", "gcamps_set_candset", "gcamps_disentangle", "gcamps_expectation",
+    "gcamps_statevector", "gcamps_amplitude", "gcamps_get_tableau", "gcamps_get_bond_dims",
+    "gcamps_get_fidelity", "gcamps_get_choice_log", "gcamps_get_site", "gcamps_get_stats",
+    "gcamps_last_error",
+]
+
+
+class GcampsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n", C.c_int32), ("chi_max", C.c_int32), ("cutoff", C.c_double),
+                ("score_prec", C.c_int32), ("near_tie", C.c_double), ("tie_tol", C.c_double),
+                ("max_sweeps", C.c_int32), ("auto_disentangle", C.c_int32),
+                ("max_candidates", C.c_int32)]
+
+
+class CWord(C.Structure):
+    _fields_ = [("len", C.c_int32), ("gens", C.POINTER(C.c_uint8)), ("weyl", C.c_int32 * 4)]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(python -m paper_2511_06672_amd.build)")
+    lib = C.CDLL(path)
+    P, I32, I64, D, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    sig = {
+        "gcamps_workspace_bytes": [C.POINTER(Config), C.POINTER(SZ)],
+        "gcamps_init": [C.POINTER(Config), P, SZ, P, C.POINTER(P)],
+        "gcamps_destroy": [P],
+        "gcamps_apply_clifford": [P, I32, C.POINTER(CWord)],
+        "gcamps_apply_clifford_layer": [P, C.POINTER(I32), C.POINTER(CWord), I32],
+        "gcamps_apply_phase_rotation": [P, I32, C.POINTER(D)],
+        "gcamps_candset_create": [I32, C.POINTER(CWord), I32, C.POINTER(P)],
+        "gcamps_candset_destroy": [P],
+        "gcamps_set_candset": [P, P],
+        "gcamps_disentangle": [P, P, C.POINTER(I32), C.POINTER(I32)],
+        "gcamps_expectation": [P, C.POINTER(C.c_int8), C.POINTER(C.c_int8), I32, C.POINTER(D)],
+        "gcamps_statevector": [P, P, P, SZ],
+        "gcamps_amplitude": [P, C.POINTER(C.c_int8), C.POINTER(D)],
+        "gcamps_get_tableau": [P, C.POINTER(I32)],
+        "gcamps_get_bond_dims": [P, C.POINTER(I32)],
+        "gcamps_get_fidelity": [P, C.POINTER(D)],
+        "gcamps_get_choice_log": [P, C.POINTER(I32), I64, C.POINTER(I64)],
+        "gcamps_get_site": [P, I32, C.POINTER(D), I64, C.POINTER(I32)],
+        "gcamps_get_stats": [P, C.POINTER(D)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = I32
+    lib.gcamps_last_error.argtypes = []
+    lib.gcamps_last_error.restype = C.c_char_p
+    return lib
+
+
+_LIB: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _check(code: int):
+    if code != GCAMPS_OK:
+        raise GcampsError(code, lib().gcamps_last_error().decode())
+
+
+def _words(words) -> tuple:
+    """Marshal workload Word objects (gens, weyl) into a CWord array (keeps buffers alive)."""
+    arr = (CWord * len(words))()
+    keep = []
+    for i, w in enumerate(words):
+        g = (C.c_uint8 * max(1, len(w.gens)))(*w.gens)
+        keep.append(g)
+        arr[i].len = len(w.gens)
+        arr[i].gens = C.cast(g, C.POINTER(C.c_uint8))
+        for j in range(4):
+            arr[i].weyl[j] = int(w.weyl[j])
+    return arr, keep
+
+
+def make_config(d, n, chi_max, cutoff, score_prec=SCORE_FP64, near_tie=1e-4, tie_tol=1e-10,
+                max_sweeps=2, auto_disentangle=True, max_candidates=512) -> Config:
+    return Config(d, n, chi_max, cutoff, score_prec, near_tie, tie_tol, max_sweeps,
+                  1 if auto_disentangle else 0, max_candidates)
+
+
+def workspace_bytes(cfg: Config) -> int:
+    b = C.c_size_t(0)
+    _check(lib().gcamps_workspace_bytes(C.byref(cfg), C.byref(b)))
+    return b.value
+
+
+class CandSet:
+    def __init__(self, d: int, words):
+        arr, keep = _words(words)
+        h = C.c_void_p()
+        _check(lib().gcamps_candset_create(d, arr, len(words), C.byref(h)))
+        self.handle = h
+        self.d = d
+        self.count = len(words)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.gcamps_candset_destroy(self.handle)
+            self.handle = None
+
+
+class State:
+    """One GCAMPS state psi = C|MPS> on a GPU (gcamps_ctx)."""
+
+    def __init__(self, cfg: Config, device: str = "cuda:0", stream=None):
+        import torch
+        self.cfg = cfg
+        self.d, self.n = cfg.d, cfg.n
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(cfg)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib().gcamps_init(C.byref(cfg), C.c_void_p(aligned), nbytes,
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+        self._candset = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gcamps_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- operations
+    def apply_clifford(self, site: int, word):
+        arr, keep = _words([word])
+        _check(lib().gcamps_apply_clifford(self.handle, site, arr))
+
+    def apply_clifford_layer(self, sites: Sequence[int], words):
+        if not sites:
+            return
+        arr, keep = _words(words)
+        s = (C.c_int32 * len(sites))(*sites)
+        _check(lib().gcamps_apply_clifford_layer(self.handle, s, arr, len(sites)))
+
+    def apply_phase_rotation(self, site: int, phi: Sequence[float]):
+        a = (C.c_double * self.d)(*phi)
+        _check(lib().gcamps_apply_phase_rotation(self.handle, site, a))
+
+    def set_candset(self, cs: CandSet):
+        self._candset = cs
+        _check(lib().gcamps_set_candset(self.handle, cs.handle))
+
+    def disentangle(self, cs: Optional[CandSet] = None):
+        sw, ch = C.c_int32(0), C.c_int32(0)
+        _check(lib().gcamps_disentangle(self.handle, cs.handle if cs else None, C.byref(sw),
+                                        C.byref(ch)))
+        return sw.value, ch.value
+
+    def expectation(self, x, z, p: int = 0) -> complex:
+        xa = (C.c_int8 * self.n)(*[int(v) for v in x])
+        za = (C.c_int8 * self.n)(*[int(v) for v in z])
+        out = (C.c_double * 2)()
+        _check(lib().gcamps_expectation(self.handle, xa, za, p, out))
+        return complex(out[0], out[1])
+
+    def statevector(self) -> np.ndarray:
+        import torch
+        D = self.d ** self.n
+        out = torch.empty(2 * D, dtype=torch.float64, device=self.device)
+        scratch = torch.empty(6 * D, dtype=torch.float64, device=self.device)
+        _check(lib().gcamps_statevector(self.handle, C.c_void_p(out.data_ptr()),
+                                        C.c_void_p(scratch.data_ptr()), scratch.numel() * 8))
+        v = out.cpu().numpy()
+        return v[0::2] + 1j * v[1::2]
+
+    def amplitude(self, digits) -> complex:
+        a = (C.c_int8 * self.n)(*[int(v) for v in digits])
+        out = (C.c_double * 2)()
+        _check(lib().gcamps_amplitude(self.handle, a, out))
+        return complex(out[0], out[1])
+
+    # ---------------------------------------------------------------- getters
+    def tableau(self) -> np.ndarray:
+        n = self.n
+        buf = (C.c_int32 * (2 * n * (2 * n + 1)))()
+        _check(lib().gcamps_get_tableau(self.handle, buf))
+        return np.frombuffer(buf, dtype=np.int32).reshape(2 * n, 2 * n + 1).astype(np.int64)
+
+    def bond_dims(self) -> List[int]:
+        buf = (C.c_int32 * (self.n - 1))()
+        _check(lib().gcamps_get_bond_dims(self.handle, buf))
+        return list(buf)
+
+    def fidelity(self) -> float:
+        f = C.c_double(0)
+        _check(lib().gcamps_get_fidelity(self.handle, C.byref(f)))
+        return f.value
+
+    def choice_log(self) -> np.ndarray:
+        ln = C.c_int64(0)
+        _check(lib().gcamps_get_choice_log(self.handle, None, 0, C.byref(ln)))
+        buf = (C.c_int32 * (4 * max(1, ln.value)))()
+        _check(lib().gcamps_get_choice_log(self.handle, buf, ln.value, C.byref(ln)))
+        return np.frombuffer(buf, dtype=np.int32)[:4 * ln.value].reshape(-1, 4).copy()
+
+    def site(self, i: int) -> np.ndarray:
+        dims = (C.c_int32 * 3)()
+        _check(lib().gcamps_get_site(self.handle, i, None, 0, dims))
+        cnt = dims[0] * dims[1] * dims[2]
+        buf = (C.c_double * (2 * cnt))()
+        _check(lib().gcamps_get_site(self.handle, i, buf, cnt, dims))
+        v = np.frombuffer(buf, dtype=np.float64)
+        return (v[0::2] + 1j * v[1::2]).reshape(dims[0], dims[1], dims[2])
+
+    def stats(self) -> dict:
+        out = (C.c_double * 8)()
+        _check(lib().gcamps_get_stats(self.handle, out))
+        keys = ["gates", "bonds_scored", "rescored", "degenerate_cuts", "score_flops",
+                "factor_flops", "score_ms", "host_ms"]
+        return dict(zip(keys, list(out)))
+
+
+def run_circuit(state: State, circuit, phases_override=None):
+    """Apply a workload circuit layer by layer (bricks as one layer launch, then phases)."""
+    for layer in circuit.layers:
+        if layer.bricks:
+            state.apply_clifford_layer([b.site for b in layer.bricks], [b.word for b in layer.bricks])
+        for ph in layer.phases:
+            phi = ph.phi
+            if phases_override is not None and ph.param >= 0:
+                phi = phases_override[ph.param]
+            state.apply_phase_rotation(ph.site, phi)
+    return state
