@@ -177,11 +177,14 @@ int32_t gcamps_get_choice_log(gcamps_ctx* ctx, int32_t* out, int64_t cap, int64_
 /* Site tensor `site` (chi_l, d, chi_r) as complex128 into host memory out
  * (capacity cap complex values); dims written to dims[3]. */
 int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap, int32_t dims[3]);
-/* Statistics: [0] non-Clifford gates applied, [1] bonds scored, [2] candidates
- * re-scored in FP64 (FP32 mode), [3] degenerate cuts flagged, [4] scoring flops
- * (algorithmic), [5] factorisation flops (algorithmic), [6] scoring kernel time
- * in ms (device events), [7] total time inside gcamps_* in ms (host). */
-int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[8]);
+/* Statistics (16 doubles): [0] non-Clifford gates applied, [1] bonds scored,
+ * [2] candidates re-scored in FP64 (FP32 mode), [3] degenerate cuts flagged,
+ * [4] algorithmic flops of full-set scoring, [5] algorithmic flops of the Gram products of
+ * the factorisations, [6] full-set scoring kernel time in ms (device events), [7] total time
+ * inside gcamps_* calls in ms (host clock), [8] flops of the FP64 window re-score, [9] its
+ * kernel time in ms, [10] scoring launches, [11] of which on the tiled MFMA path, [12] their
+ * kernel time in ms, [13] their algorithmic flops, [14..15] reserved (0). */
+int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[16]);
 
 /* Thread-local message for the last failed call on this thread. */
 const char* gcamps_last_error(void);

@@ -148,18 +148,20 @@ struct gcamps_ctx {
   size_t pinned_bytes = 0;
   hipEvent_t stage_ev = nullptr;
   bool stage_pending = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
   // host state
   double f_est = 1.0;
   std::vector<int32_t> choice_log;
   int64_t gates = 0;
-  double stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double stats[16] = {0};
 
   ~gcamps_ctx() {
     if (pinned) (void)hipHostFree(pinned);
     if (stage_ev) (void)hipEventDestroy(stage_ev);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (ev2) (void)hipEventDestroy(ev2);
+    if (ev3) (void)hipEventDestroy(ev3);
   }
 
   // ---------------------------------------------------------------- staging
@@ -328,29 +330,40 @@ struct gcamps_ctx {
                      z64{1.0, 0.0}, 0, 0);
         const int mm = std::min(cl * d, d * cr), kk = std::max(cl * d, d * cr);
         const size_t pcap = lay.ncand * lay.ntp * 2;
+        const double pflops = 4.0 * mm * mm * kk + 8.0 * std::pow((double)d, 4) * cl * cr;
         GC_HIP(hipEventRecord(ev0, stream));
+        launch_score(stream, prec, d, cl, cr, theta, q64, q32, nullptr, ncand, nullptr, s2, partial, pcap);
+        GC_HIP(hipEventRecord(ev1, stream));
         if (prec == GCAMPS_SCORE_FP64) {
-          launch_score(stream, GCAMPS_SCORE_FP64, d, cl, cr, theta, q64, q32, nullptr, ncand, nullptr, s2, partial,
-                       pcap);
           launch_select(stream, ncand, s2, cfg.tie_tol, st);
         } else {
-          launch_score(stream, GCAMPS_SCORE_FP32, d, cl, cr, theta, q64, q32, nullptr, ncand, nullptr, s2, partial,
-                       pcap);
           launch_window(stream, ncand, s2, cfg.near_tie, wlist, st);
+          GC_HIP(hipEventRecord(ev2, stream));
           launch_score(stream, GCAMPS_SCORE_FP64, d, cl, cr, theta, q64, q32, wlist, ncand, &st->nwindow, s2w,
                        partial, pcap);
+          GC_HIP(hipEventRecord(ev3, stream));
           launch_select_window(stream, wlist, s2w, cfg.tie_tol, st);
         }
-        GC_HIP(hipEventRecord(ev1, stream));
-        stats[4] += (double)ncand * (4.0 * mm * mm * kk + 8.0 * std::pow((double)d, 4) * cl * cr);
+        stats[4] += (double)ncand * pflops;
+        stats[10] += 1;
+        if (mm > 96) stats[11] += 1;
         launch_apply_q(stream, d, cl, cr, st, q64, theta);
         launch_tableau_right_mult(stream, n, d, i, st, qinv, tx, tz, tp);
         DevStatus h = factorize(theta, cl * d, d * cr, 0, ltr ? 1 : 0, Lbuf, Rbuf);
         float ms = 0.f;
         GC_HIP(hipEventElapsedTime(&ms, ev0, ev1));
         stats[6] += ms;
+        if (mm > 96) {
+          stats[12] += ms;
+          stats[13] += (double)ncand * pflops;
+        }
         stats[1] += 1;
-        if (prec != GCAMPS_SCORE_FP64) stats[2] += h.nwindow;
+        if (prec != GCAMPS_SCORE_FP64) {
+          stats[2] += h.nwindow;
+          stats[8] += (double)h.nwindow * pflops;
+          GC_HIP(hipEventElapsedTime(&ms, ev2, ev3));
+          stats[9] += ms;
+        }
         std::swap(site[i], Lbuf);
         std::swap(site[i + 1], Rbuf);
         chi[i + 1] = h.kept;
@@ -481,6 +494,8 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
     GC_HIP(hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming));
     GC_HIP(hipEventCreate(&c->ev0));
     GC_HIP(hipEventCreate(&c->ev1));
+    GC_HIP(hipEventCreate(&c->ev2));
+    GC_HIP(hipEventCreate(&c->ev3));
     // |0...0>: every site tensor (1, d, 1) = e_0, tableau C = I
     c->chi.assign(n + 1, 1);
     c->centre = 0;
@@ -756,7 +771,14 @@ static void statevector_impl(gcamps_ctx* ctx, z64* out, z64* scratch) {
     px[x] = p;
     for (int i = 0; i < n; ++i) bd[(size_t)x * n + i] = (int8_t)bz[i];
   }
-  int* d_aidx = reinterpret_cast<int*>(ctx->B);
+  // validation-only table: allocated per call
+  char* tbl = nullptr;
+  GC_HIP(hipMalloc(reinterpret_cast<void**>(&tbl), (size_t)D * (2 * sizeof(int) + n)));
+  struct FreeTbl {
+    char* p;
+    ~FreeTbl() { (void)hipFree(p); }
+  } free_tbl{tbl};
+  int* d_aidx = reinterpret_cast<int*>(tbl);
   int* d_px = d_aidx + D;
   int8_t* d_bd = reinterpret_cast<int8_t*>(d_px + D);
   GC_HIP(hipMemcpy(d_aidx, aidx.data(), D * sizeof(int), hipMemcpyHostToDevice));
@@ -771,8 +793,6 @@ int32_t gcamps_statevector(gcamps_ctx* ctx, void* dev_out, void* dev_scratch, si
     GC_CHECK(ctx && dev_out && dev_scratch, GCAMPS_EINVAL, "null argument");
     const long long D = dense_dim(ctx);
     GC_CHECK(scratch_bytes >= (size_t)3 * D * sizeof(z64), GCAMPS_EWORKSPACE, "scratch smaller than 3*16*d^n bytes");
-    GC_CHECK((size_t)D * (2 * sizeof(int) + ctx->n) <= ctx->lay.slot_elems * sizeof(z64), GCAMPS_EUNSUPPORTED,
-             "workspace too small for the dense table");
     statevector_impl(ctx, reinterpret_cast<z64*>(dev_out), reinterpret_cast<z64*>(dev_scratch));
   });
 }
@@ -859,10 +879,10 @@ int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap,
   });
 }
 
-int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[8]) {
+int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[16]) {
   return guarded(nullptr, [&] {
     GC_CHECK(ctx && out, GCAMPS_EINVAL, "null argument");
-    for (int i = 0; i < 8; ++i) out[i] = ctx->stats[i];
+    for (int i = 0; i < 16; ++i) out[i] = ctx->stats[i];
   });
 }
 

@@ -48,6 +48,18 @@ __host__ __device__ __forceinline__ T cabs2(cx<T> a) {
   return a.re * a.re + a.im * a.im;
 }
 
+// ----------------------------------------------------------------- MFMA 16x16x4 accumulators
+// Row of accumulator item q in lane `lane` (column is lane % 16).  Measured on gfx950:
+// v_mfma_f64_16x16x4f64 places row 4q + lane/16, v_mfma_f32_16x16x4f32 row 4(lane/16) + q.
+__device__ __forceinline__ int mfma_row_f64(int lane, int q) { return 4 * q + (lane >> 4); }
+__device__ __forceinline__ int mfma_row_f32(int lane, int q) { return 4 * (lane >> 4) + q; }
+template <typename T>
+__device__ __forceinline__ int mfma_row(int lane, int q);
+template <>
+__device__ __forceinline__ int mfma_row<double>(int lane, int q) { return mfma_row_f64(lane, q); }
+template <>
+__device__ __forceinline__ int mfma_row<float>(int lane, int q) { return mfma_row_f32(lane, q); }
+
 // ----------------------------------------------------------------- errors
 struct Error {
   int code;

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* _
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int q = 0; q < 4; ++q) {
-        int row = m0 + wr + i * 16 + 4 * (lane >> 4) + q;
+        int row = m0 + wr + i * 16 + mfma_row_f64(lane, q);
         int col = n0 + wc + j * 16 + (lane & 15);
         if (row < M && col < N) {
           z64 v = {alpha.re * accr[i][j][q] - alpha.im * acci[i][j][q],
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64*
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 2; ++j)
         for (int q = 0; q < 4; ++q) {
-          int row = wr + i * 16 + 4 * (lane >> 4) + q;
+          int row = wr + i * 16 + mfma_row_f64(lane, q);
           int col = wc + j * 16 + (lane & 15);
           b_re[row * SLD + col] = accr[i][j][q];
           b_im[row * SLD + col] = acci[i][j][q];
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64*
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 2; ++j)
         for (int q = 0; q < 4; ++q) {
-          int row = wr + i * 16 + 4 * (lane >> 4) + q;
+          int row = wr + i * 16 + mfma_row_f64(lane, q);
           int col = wc + j * 16 + (lane & 15);
           Gp[(size_t)pair_index(P, row, step, nb) * mp + pair_index(Q, col, step, nb)] =
               z64{accr[i][j][q], acci[i][j][q]};
@@ -454,7 +454,7 @@ __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64*
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 2; ++j)
         for (int q = 0; q < 4; ++q) {
-          int row = wr + i * 16 + 4 * (lane >> 4) + q;
+          int row = wr + i * 16 + mfma_row_f64(lane, q);
           int col = wc + j * 16 + (lane & 15);
           Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, col, step, nb)] = z64{accr[i][j][q], acci[i][j][q]};
         }
@@ -743,6 +743,8 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
 }
 
 void linalg_set_attributes() {
+  // Large dynamic LDS for the Jacobi kernels; a failure here only means the default limit
+  // already allows it, so the sticky error state is cleared afterwards.
   const int lim = 160 * 1024;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_small), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lim);
@@ -750,6 +752,7 @@ void linalg_set_attributes() {
                             lim);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_jblock_apply), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lim);
+  (void)hipGetLastError();
 }
 
 void launch_rownorm2(hipStream_t s, const z64* B, int m, int k, int ldb, double* out) {

@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_score_tiled(int d, int chil, int chir, 
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int q = 0; q < 4; ++q) {
-        int row = r0 + wr + i * 16 + 4 * (lane >> 4) + q;
+        int row = r0 + wr + i * 16 + mfma_row<T>(lane, q);
         int col = c0 + wc + j * 16 + (lane & 15);
         if (row < m && col < m) {
           double re = (double)accr[i][j][q], im = (double)acci[i][j][q];

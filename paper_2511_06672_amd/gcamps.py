@@ -253,10 +253,11 @@ class State:
         return (v[0::2] + 1j * v[1::2]).reshape(dims[0], dims[1], dims[2])
 
     def stats(self) -> dict:
-        out = (C.c_double * 8)()
+        out = (C.c_double * 16)()
         _check(lib().gcamps_get_stats(self.handle, out))
         keys = ["gates", "bonds_scored", "rescored", "degenerate_cuts", "score_flops",
-                "factor_flops", "score_ms", "host_ms"]
+                "factor_flops", "score_ms", "host_ms", "rescore_flops", "rescore_ms",
+                "score_launches", "tiled_launches", "tiled_ms", "tiled_flops", "r14", "r15"]
         return dict(zip(keys, list(out)))
 
 

@@ -37,10 +37,11 @@ def aligned_error(psi, ref):
     return float(np.max(np.abs(psi * (ov / abs(ov)) - ref)))
 
 
-def run_pair(g, circuit, cands, chi_max, cutoff, prec=0, auto=True, max_sweeps=2, near_tie=1e-3):
+def run_pair(g, circuit, cands, chi_max, cutoff, prec=0, auto=True, max_sweeps=2, near_tie=1e-3,
+             max_candidates=None):
     cfg = g.make_config(circuit.d, circuit.n, chi_max, cutoff, score_prec=prec, near_tie=near_tie,
                         max_sweeps=max_sweeps, auto_disentangle=auto,
-                        max_candidates=max(1, len(cands)))
+                        max_candidates=max_candidates or max(1, len(cands)))
     st = g.State(cfg)
     if cands:
         st.set_candset(g.CandSet(circuit.d, cands))
@@ -146,7 +147,7 @@ def test_large_matrices_block_paths(g):
     d, n = 3, 8
     say("large matrices: saturating phase gates without disentangling")
     c = brickwork_circuit(d, n, 12, 12, seed=91)
-    st, orc = run_pair(g, c, [], 81, 0.0, auto=False)
+    st, orc = run_pair(g, c, [], 81, 0.0, auto=False, max_candidates=64)
     assert max(st.bond_dims()) >= 27
     assert st.bond_dims() == orc.mps.bond_dims()
     assert aligned_error(st.statevector(), simulate(c)) < 1e-10
