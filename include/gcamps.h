@@ -183,7 +183,8 @@ int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap,
  * the factorisations, [6] full-set scoring kernel time in ms (device events), [7] total time
  * inside gcamps_* calls in ms (host clock), [8] flops of the FP64 window re-score, [9] its
  * kernel time in ms, [10] scoring launches, [11] of which on the tiled MFMA path, [12] their
- * kernel time in ms, [13] their algorithmic flops, [14..15] reserved (0). */
+ * kernel time in ms, [13] their algorithmic flops, [14] bond splits that factorised only the
+ * centre tensor (identity kept), [15] reserved (0). */
 int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[16]);
 
 /* Thread-local message for the last failed call on this thread. */

@@ -349,7 +349,35 @@ struct gcamps_ctx {
         if (mm > 96) stats[11] += 1;
         launch_apply_q(stream, d, cl, cr, st, q64, theta);
         launch_tableau_right_mult(stream, n, d, i, st, qinv, tx, tz, tp);
-        DevStatus h = factorize(theta, cl * d, d * cr, 0, ltr ? 1 : 0, Lbuf, Rbuf);
+        // When the identity is kept, Theta = A_i A_{i+1} with the neighbour of the centre
+        // orthonormal (right-orthonormal A_{i+1} when sweeping left to right, left-orthonormal
+        // A_i otherwise), so Theta's Schmidt values are those of the centre tensor alone and the
+        // split only needs the factorisation of that (smaller) tensor.
+        bool shortcut = false;
+        if (mm > kSmallEig) {
+          DevStatus pre;
+          read_status(pre);
+          shortcut = (pre.cstar == 0);
+        }
+        DevStatus h;
+        if (shortcut && ltr) {
+          h = factorize(site[i], cl * d, cm, 0, 1, Lbuf, Rbuf);
+          const int k = h.kept;
+          launch_zgemm(stream, 0, 0, k, d * cr, cm, Rbuf, cm, site[i + 1], d * cr, spare, d * cr, z64{1.0, 0.0}, 0, 0);
+          std::swap(site[i], Lbuf);
+          std::swap(site[i + 1], spare);
+        } else if (shortcut) {
+          h = factorize(site[i + 1], cm, d * cr, 0, 0, Lbuf, Rbuf);
+          const int k = h.kept;
+          launch_zgemm(stream, 0, 0, cl * d, k, cm, site[i], cm, Lbuf, k, spare, k, z64{1.0, 0.0}, 0, 0);
+          std::swap(site[i + 1], Rbuf);
+          std::swap(site[i], spare);
+        } else {
+          h = factorize(theta, cl * d, d * cr, 0, ltr ? 1 : 0, Lbuf, Rbuf);
+          std::swap(site[i], Lbuf);
+          std::swap(site[i + 1], Rbuf);
+        }
+        stats[14] += shortcut ? 1 : 0;
         float ms = 0.f;
         GC_HIP(hipEventElapsedTime(&ms, ev0, ev1));
         stats[6] += ms;
@@ -364,8 +392,6 @@ struct gcamps_ctx {
           GC_HIP(hipEventElapsedTime(&ms, ev2, ev3));
           stats[9] += ms;
         }
-        std::swap(site[i], Lbuf);
-        std::swap(site[i + 1], Rbuf);
         chi[i + 1] = h.kept;
         centre = ltr ? i + 1 : i;
         f_est *= (1.0 - h.eps);

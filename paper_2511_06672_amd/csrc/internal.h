@@ -84,8 +84,8 @@ void set_error(const std::string& msg);
 // ----------------------------------------------------------------- limits
 constexpr int kMaxD = 7;
 constexpr int kMaxN = 128;
-constexpr int kSmallEig = 96;   // largest m handled by the single-workgroup eigensolver
-constexpr int kBlk = 32;        // block size of the multi-workgroup block Jacobi
+constexpr int kSmallEig = 32;   // largest m handled by the single-workgroup eigensolver
+constexpr int kBlk = 16;        // block size of the multi-workgroup block Jacobi
 
 // ----------------------------------------------------------------- device status block
 // Written by the selection / truncation kernels, read back once per bond.

@@ -1,10 +1,15 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle on seeded inputs.
 
 Bars: tableaux, choice logs and bond dimensions bit-exact; amplitudes within 1e-10
-after aligning the global phase (the tableau fixes C only up to a phase); the
-fidelity estimate within 1e-12 relative.
+after aligning the global phase (the tableau fixes C only up to a phase).  The
+fidelity estimate F = prod(1 - eps) is compared to F_TOL relative: the GPU takes the
+discarded weights eps from Gram eigen-decompositions whose eigenvalues carry an
+absolute error of order m * 2^-52 * lambda_max each, so over T truncations with up to
+m discarded values F can move by about T * m^2 * 1e-16 (1e-9 covers T = 1000, m = 100).
 """
 import sys
+
+F_TOL = 1e-9
 
 import numpy as np
 import pytest
@@ -137,7 +142,23 @@ def test_truncated_regime_parity(g):
     assert np.array_equal(st.choice_log(), oracle_log(orc))
     assert st.bond_dims() == orc.mps.bond_dims()
     assert np.array_equal(st.tableau(), orc.tab.export())
-    assert abs(st.fidelity() - orc.f_est) <= 1e-12 * orc.f_est
+    assert abs(st.fidelity() - orc.f_est) <= F_TOL * orc.f_est
+    assert aligned_error(st.statevector(), orc.statevector()) < 1e-9
+
+
+def test_truncated_regime_large_bonds(g):
+    """chi_max = 27 with many T gates: block-Jacobi splits, the centre-only split when the
+    identity is kept, and truncation, all against the oracle."""
+    d, n = 3, 10
+    say("truncated regime n=10 chi_max=27")
+    c = brickwork_circuit(d, n, 20, 20, seed=78)
+    cands = candidate_words(d, 64, 78)
+    st, orc = run_pair(g, c, cands, 27, 1e-10)
+    assert st.stats()["centre_splits"] > 0
+    assert np.array_equal(st.choice_log(), oracle_log(orc))
+    assert st.bond_dims() == orc.mps.bond_dims()
+    assert np.array_equal(st.tableau(), orc.tab.export())
+    assert abs(st.fidelity() - orc.f_est) <= F_TOL * orc.f_est
     assert aligned_error(st.statevector(), orc.statevector()) < 1e-9
 
 
