@@ -1,0 +1,63 @@
+"""Full-size parity on the headline workload (qutrits, n = 32, 40 layers, 40 T gates,
+chi_max = 256, cutoff 1e-10, 512 candidates), in the configuration bench.py times.
+
+Expected values come from tests/golden/headline_d3_n32_oracle.json, written by
+tests/golden/make_headline_reference.py, which calls only the oracle.  The GPU path
+is compared gate by gate over the gates the reference covers: disentangler choices,
+bond dimensions and the tableau (bit-exact), and the fidelity estimate (F_TOL).
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "headline_d3_n32_oracle.json")
+F_TOL = 1e-9
+
+
+def digest(tab):
+    return hashlib.sha256(np.ascontiguousarray(tab, dtype="<i8").tobytes()).hexdigest()[:16]
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp32_scored", "fp64"])
+def test_headline_against_oracle_reference(prec):
+    if not os.path.exists(GOLDEN):
+        pytest.skip("oracle reference not generated")
+    ref = json.load(open(GOLDEN))
+    import torch
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import workload
+    assert torch.cuda.is_available()
+    wl = workload("headline_d3_n32")
+    c = wl.circuit
+    ngates = ref["gates_done"]
+    print(f"[gpu-case] headline reference, {ngates} gates, prec={prec}", flush=True)
+    st = g.State(g.make_config(c.d, c.n, wl.chi_max, wl.cutoff, score_prec=prec, near_tie=1e-4,
+                               max_candidates=len(wl.candidates)))
+    st.set_candset(g.CandSet(c.d, wl.candidates))
+    gi = 0
+    prev = 0
+    for layer in c.layers:
+        if gi >= ngates:
+            break
+        if layer.bricks:
+            st.apply_clifford_layer([b.site for b in layer.bricks], [b.word for b in layer.bricks])
+        for ph in layer.phases:
+            st.apply_phase_rotation(ph.site, ph.phi)
+            r = ref["gates"][gi]
+            log = st.choice_log()
+            mine = log[prev:]
+            prev = len(log)
+            assert [list(map(int, x[1:])) for x in mine] == r["choices"], f"choices differ at gate {gi}"
+            assert st.bond_dims() == r["bond_dims"], f"bond dims differ at gate {gi}"
+            assert digest(st.tableau()) == r["tableau_sha256"], f"tableau differs at gate {gi}"
+            assert abs(st.fidelity() - r["f_est"]) <= F_TOL * r["f_est"], f"fidelity differs at gate {gi}"
+            gi += 1
+            if gi >= ngates:
+                break
+    print(f"[gpu-case] matched {gi} gates, final F {st.fidelity():.15f}", flush=True)
