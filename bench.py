@@ -135,7 +135,7 @@ def main():
                  "fidelity_rel_diff": abs(f32 - f64) / f64,
                  "equal_final_fidelity": bool(same_choices and abs(f32 - f64) <= 1e-12 * f64)}
 
-    # dominant-kernel roofline: the tiled MFMA scoring kernel (FP32 arithmetic)
+    # roofline of the Gram-purity MFMA kernel (FP32 arithmetic), timed per launch with HIP events
     tiled_ms = s32["tiled_ms"]
     roof = None
     if s32["tiled_launches"] > 0 and tiled_ms > 0:
@@ -144,7 +144,7 @@ def main():
         achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                "kernel": "k_score_tiled<float>", "launches": int(s32["tiled_launches"]),
+                "kernel": "k_gram_purity<float, 4>", "launches": int(s32["tiled_launches"]),
                 "avg_ms": per_launch_ms}
 
     cpu = None

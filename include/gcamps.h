@@ -182,8 +182,9 @@ int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap,
  * [4] algorithmic flops of full-set scoring, [5] algorithmic flops of the Gram products of
  * the factorisations, [6] full-set scoring kernel time in ms (device events), [7] total time
  * inside gcamps_* calls in ms (host clock), [8] flops of the FP64 window re-score, [9] its
- * kernel time in ms, [10] scoring launches, [11] of which on the tiled MFMA path, [12] their
- * kernel time in ms, [13] their algorithmic flops, [14] bond splits that factorised only the
+ * kernel time in ms, [10] scoring calls (bonds x passes), [11] launches of the Gram-purity MFMA
+ * kernel (full-set scoring), [12] their summed kernel time in ms (device events around each
+ * launch), [13] their algorithmic flops (4 m^2 k per candidate), [14] bond splits that factorised only the
  * centre tensor (identity kept), [15] reserved (0). */
 int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[16]);
 

@@ -37,7 +37,7 @@ struct Layout {
   size_t slot_elems, theta_elems, mcap, m_pad, ncand, ntp;
   int nslots;
   size_t off_slots, off_theta, off_G, off_U, off_Z, off_Utmp, off_B, off_B2, off_sig2, off_sig, off_lam,
-      off_perm, off_eigG, off_eigV, off_flags, off_s2, off_s2w, off_wlist, off_partial, off_q64, off_q32,
+      off_perm, off_eigG, off_eigV, off_flags, off_s2, off_s2w, off_wlist, off_partial, off_nbuf, nbuf_bytes, off_q64, off_q32,
       off_qinv, off_tab, off_target, off_weyl, off_err, off_status, off_luts, off_sites, total;
 };
 
@@ -51,7 +51,7 @@ Layout make_layout(const gcamps_config& c) {
   L.m_pad = ((chicap + 63) / 64) * 64;
   L.ncand = std::max(1, c.max_candidates);
   size_t nt = (chicap + 63) / 64;
-  L.ntp = nt * (nt + 1) / 2;
+  L.ntp = nt * (nt + 1) / 2;  // 64-wide tiles (the FP32 path uses 128-wide, fewer)
   L.nslots = c.n + 3;  // n sites + L, R, one spare
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -78,6 +78,9 @@ Layout make_layout(const gcamps_config& c) {
   L.off_s2w = take(L.ncand * sizeof(double));
   L.off_wlist = take(L.ncand * sizeof(int));
   L.off_partial = take(L.ncand * L.ntp * 2 * sizeof(double));
+  // rotated candidate matrices of the tiled scorer: up to 64 candidates of m x k complex128
+  L.nbuf_bytes = (size_t)std::min<size_t>(64, L.ncand) * L.theta_elems * sizeof(z64);
+  L.off_nbuf = take(L.nbuf_bytes);
   const size_t D4 = d * d * d * d;
   L.off_q64 = take(L.ncand * D4 * sizeof(z64));
   L.off_q32 = take(L.ncand * D4 * sizeof(c32));
@@ -128,6 +131,7 @@ struct gcamps_ctx {
   DevStatus* st = nullptr;
   z64 *theta = nullptr, *G = nullptr, *U = nullptr, *Z = nullptr, *Utmp = nullptr, *B = nullptr, *B2 = nullptr;
   double *sig2 = nullptr, *sig = nullptr, *lam = nullptr, *s2 = nullptr, *s2w = nullptr, *partial = nullptr;
+  void* nbuf = nullptr;
   int *perm = nullptr, *wlist = nullptr;
   z64* q64 = nullptr;
   c32* q32 = nullptr;
@@ -149,6 +153,7 @@ struct gcamps_ctx {
   hipEvent_t stage_ev = nullptr;
   bool stage_pending = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  std::vector<hipEvent_t> gram_ev;  // event pairs around the Gram-purity launches of one bond
   // host state
   double f_est = 1.0;
   std::vector<int32_t> choice_log;
@@ -162,6 +167,7 @@ struct gcamps_ctx {
     if (ev1) (void)hipEventDestroy(ev1);
     if (ev2) (void)hipEventDestroy(ev2);
     if (ev3) (void)hipEventDestroy(ev3);
+    for (auto e : gram_ev) (void)hipEventDestroy(e);
   }
 
   // ---------------------------------------------------------------- staging
@@ -332,7 +338,9 @@ struct gcamps_ctx {
         const size_t pcap = lay.ncand * lay.ntp * 2;
         const double pflops = 4.0 * mm * mm * kk + 8.0 * std::pow((double)d, 4) * cl * cr;
         GC_HIP(hipEventRecord(ev0, stream));
-        launch_score(stream, prec, d, cl, cr, theta, q64, q32, nullptr, ncand, nullptr, s2, partial, pcap);
+        int gram_used = 0;
+        launch_score(stream, prec, d, cl, cr, theta, q64, q32, nullptr, ncand, nullptr, s2, partial, pcap, nbuf,
+                     lay.nbuf_bytes, gram_ev.data(), (int)gram_ev.size(), &gram_used);
         GC_HIP(hipEventRecord(ev1, stream));
         if (prec == GCAMPS_SCORE_FP64) {
           launch_select(stream, ncand, s2, cfg.tie_tol, st);
@@ -340,13 +348,12 @@ struct gcamps_ctx {
           launch_window(stream, ncand, s2, cfg.near_tie, wlist, st);
           GC_HIP(hipEventRecord(ev2, stream));
           launch_score(stream, GCAMPS_SCORE_FP64, d, cl, cr, theta, q64, q32, wlist, ncand, &st->nwindow, s2w,
-                       partial, pcap);
+                       partial, pcap, nbuf, lay.nbuf_bytes);
           GC_HIP(hipEventRecord(ev3, stream));
           launch_select_window(stream, wlist, s2w, cfg.tie_tol, st);
         }
         stats[4] += (double)ncand * pflops;
         stats[10] += 1;
-        if (mm > 96) stats[11] += 1;
         launch_apply_q(stream, d, cl, cr, st, q64, theta);
         launch_tableau_right_mult(stream, n, d, i, st, qinv, tx, tz, tp);
         // When the identity is kept, Theta = A_i A_{i+1} with the neighbour of the centre
@@ -381,9 +388,14 @@ struct gcamps_ctx {
         float ms = 0.f;
         GC_HIP(hipEventElapsedTime(&ms, ev0, ev1));
         stats[6] += ms;
-        if (mm > 96) {
-          stats[12] += ms;
-          stats[13] += (double)ncand * pflops;
+        if (gram_used > 0) {  // Gram-purity kernel alone: algorithmic 4 m^2 k flop per candidate
+          for (int e = 0; e < gram_used; ++e) {
+            float gm = 0.f;
+            GC_HIP(hipEventElapsedTime(&gm, gram_ev[2 * e], gram_ev[2 * e + 1]));
+            stats[12] += gm;
+          }
+          stats[11] += gram_used;
+          stats[13] += (double)ncand * 4.0 * mm * mm * kk;
         }
         stats[1] += 1;
         if (prec != GCAMPS_SCORE_FP64) {
@@ -502,6 +514,7 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
     c->s2w = reinterpret_cast<double*>(w + lay.off_s2w);
     c->wlist = reinterpret_cast<int*>(w + lay.off_wlist);
     c->partial = reinterpret_cast<double*>(w + lay.off_partial);
+    c->nbuf = w + lay.off_nbuf;
     c->q64 = reinterpret_cast<z64*>(w + lay.off_q64);
     c->q32 = reinterpret_cast<c32*>(w + lay.off_q32);
     c->qinv = reinterpret_cast<uint32_t*>(w + lay.off_qinv);
@@ -522,6 +535,8 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
     GC_HIP(hipEventCreate(&c->ev1));
     GC_HIP(hipEventCreate(&c->ev2));
     GC_HIP(hipEventCreate(&c->ev3));
+    c->gram_ev.resize(64);
+    for (auto& e : c->gram_ev) GC_HIP(hipEventCreate(&e));
     // |0...0>: every site tensor (1, d, 1) = e_0, tableau C = I
     c->chi.assign(n + 1, 1);
     c->centre = 0;

@@ -60,10 +60,13 @@ void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* s
 // Candidate scores S2_c for the candidates cand_list[0..count) (or 0..count when cand_list is
 // null), in FP64 (prec 0) or FP32 (prec 1) arithmetic.  nlimit (nullable): device count that
 // overrides `count` (the list length is then only known on the device).  partial: scratch of
-// count * tiles doubles for the tiled path.
+// count * tiles doubles for the tiled path; nbuf: scratch for the rotated matrices of a chunk
+// of candidates (the tiled path processes as many candidates per launch as fit).  evs: optional
+// event pairs recorded around each Gram-purity launch (count returned in *evused).
 void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64* theta,
                   const z64* q64, const c32* q32, const int* cand_list, int count,
-                  const int* nlimit, double* s2, double* partial, size_t partial_cap);
+                  const int* nlimit, double* s2, double* partial, size_t partial_cap, void* nbuf,
+                  size_t nbuf_bytes, hipEvent_t* evs = nullptr, int evcap = 0, int* evused = nullptr);
 void launch_select(hipStream_t s, int count, const double* s2, double tie_tol, DevStatus* st);
 // Low-precision window: list (ascending index) of candidates with s2lp <= min + window; the
 // list length goes to st->nwindow.

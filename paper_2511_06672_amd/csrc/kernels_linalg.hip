@@ -199,53 +199,40 @@ __device__ __forceinline__ bool rot_params(double a, double b, double gr, double
   return true;
 }
 
-struct RotLds {
-  double *c, *s, *pr, *pi, *na, *nb;
-  int* on;
-};
-
-// One cyclic sweep (mp - 1 parallel steps) on the Hermitian H held as re/im planes (ld ldh) in
-// LDS.  The rotations are accumulated into V: LDS planes (vr, vi, ld ldv) when vr != null, else
-// the complex global matrix Vg (ld ldvg) restricted to its first vvalid columns.
-template <bool VLDS>
-__device__ void sweep_planes(double* __restrict__ hr, double* __restrict__ hi, int ldh, int mp,
-                             const unsigned char* __restrict__ tab, double* __restrict__ vr, double* __restrict__ vi,
-                             int ldv, z64* __restrict__ Vg, int ldvg, int vrows, int vvalid, RotLds R,
-                             const JacobiArgs& ja, int* any) {
-  const int t = threadIdx.x, nt = blockDim.x, half = mp / 2;
+// A sequence of parallel Jacobi steps on the Hermitian H (2*half indices, half <= 16) held as
+// two re/im plane pairs in LDS (double buffer).  Step s uses the pairs tab[s][k] = (p, q).  Each
+// thread recomputes the rotation parameters it needs from the old buffer, writes its 2x2 blocks
+// into the new buffer and rotates its eigenvector entries (V planes, in place), so a step
+// needs one barrier.  Returns the index (0/1) of the buffer holding the result; *any is set when
+// a rotation happened.
+__device__ int jacobi_steps(double* __restrict__ h0r, double* __restrict__ h0i, double* __restrict__ h1r,
+                            double* __restrict__ h1i, int ldh, int half, const unsigned char* __restrict__ tab,
+                            int nsteps, double* __restrict__ vr, double* __restrict__ vi, int ldv, int vrows,
+                            const JacobiArgs& ja, int* any) {
+  const int t = threadIdx.x, nt = blockDim.x;
   const float inv_half = 1.0f / (float)half;
-  for (int step = 0; step < mp - 1; ++step) {
-    const unsigned char* pt = tab + step * mp;
-    for (int k = t; k < half; k += nt) {
-      const int p = pt[2 * k], q = pt[2 * k + 1];
-      double c, s, pr, pi, na, nb;
-      const bool ok = rot_params(hr[p * ldh + p], hr[q * ldh + q], hr[p * ldh + q], hi[p * ldh + q], ja, c, s, pr, pi,
-                                 na, nb);
-      R.on[k] = ok ? 1 : 0;
-      if (ok) {
-        R.c[k] = c;
-        R.s[k] = s;
-        R.pr[k] = pr;
-        R.pi[k] = pi;
-        R.na[k] = na;
-        R.nb[k] = nb;
-        *any = 1;
-      }
-    }
-    __syncthreads();
+  int cur = 0;
+  for (int step = 0; step < nsteps; ++step) {
+    const unsigned char* pt = tab + step * 2 * half;
+    const double* ir = cur ? h1r : h0r;
+    const double* ii = cur ? h1i : h0i;
+    double* orr = cur ? h0r : h1r;
+    double* oi = cur ? h0i : h1i;
     for (int idx = t; idx < half * half; idx += nt) {
       const int k1 = (int)(((float)idx + 0.5f) * inv_half), k2 = idx - k1 * half;
-      const int f1 = R.on[k1], f2 = R.on[k2];
-      if (!f1 && !f2) continue;
       const int p1 = pt[2 * k1], q1 = pt[2 * k1 + 1], p2 = pt[2 * k2], q2 = pt[2 * k2 + 1];
-      double ar = hr[p1 * ldh + p2], ai = hi[p1 * ldh + p2];  // (p1, p2)
-      double br = hr[p1 * ldh + q2], bi = hi[p1 * ldh + q2];  // (p1, q2)
-      double cr = hr[q1 * ldh + p2], ci = hi[q1 * ldh + p2];  // (q1, p2)
-      double dr = hr[q1 * ldh + q2], di = hi[q1 * ldh + q2];  // (q1, q2)
+      double c1, s1, pr1, pi1, na1, nb1, c2, s2, pr2, pi2, na2, nb2;
+      const bool f1 = rot_params(ir[p1 * ldh + p1], ir[q1 * ldh + q1], ir[p1 * ldh + q1], ii[p1 * ldh + q1], ja, c1, s1,
+                                 pr1, pi1, na1, nb1);
+      const bool f2 = rot_params(ir[p2 * ldh + p2], ir[q2 * ldh + q2], ir[p2 * ldh + q2], ii[p2 * ldh + q2], ja, c2, s2,
+                                 pr2, pi2, na2, nb2);
+      double ar = ir[p1 * ldh + p2], ai = ii[p1 * ldh + p2];
+      double br = ir[p1 * ldh + q2], bi = ii[p1 * ldh + q2];
+      double cr = ir[q1 * ldh + p2], ci = ii[q1 * ldh + p2];
+      double dr = ir[q1 * ldh + q2], di = ii[q1 * ldh + q2];
       if (f1) {  // rows: r_p' = c r_p - s ph r_q ; r_q' = s r_p + c ph r_q
-        const double c1 = R.c[k1], s1 = R.s[k1], pr = R.pr[k1], pi = R.pi[k1];
-        double xr = pr * cr - pi * ci, xi = pr * ci + pi * cr;  // ph * (q1, p2)
-        double yr = pr * dr - pi * di, yi = pr * di + pi * dr;  // ph * (q1, q2)
+        const double xr = pr1 * cr - pi1 * ci, xi = pr1 * ci + pi1 * cr;
+        const double yr = pr1 * dr - pi1 * di, yi = pr1 * di + pi1 * dr;
         const double nar = c1 * ar - s1 * xr, nai = c1 * ai - s1 * xi;
         const double nbr = c1 * br - s1 * yr, nbi = c1 * bi - s1 * yi;
         cr = s1 * ar + c1 * xr;
@@ -258,9 +245,9 @@ __device__ void sweep_planes(double* __restrict__ hr, double* __restrict__ hi, i
         bi = nbi;
       }
       if (f2) {  // cols: c_p' = c c_p - s conj(ph) c_q ; c_q' = s c_p + c conj(ph) c_q
-        const double c2 = R.c[k2], s2 = R.s[k2], pr = R.pr[k2], pi = -R.pi[k2];
-        double xr = pr * br - pi * bi, xi = pr * bi + pi * br;  // conj(ph) * (p1, q2)
-        double yr = pr * dr - pi * di, yi = pr * di + pi * dr;  // conj(ph) * (q1, q2)
+        const double pr = pr2, pi = -pi2;
+        const double xr = pr * br - pi * bi, xi = pr * bi + pi * br;
+        const double yr = pr * dr - pi * di, yi = pr * di + pi * dr;
         const double nar = c2 * ar - s2 * xr, nai = c2 * ai - s2 * xi;
         const double ncr = c2 * cr - s2 * yr, nci = c2 * ci - s2 * yi;
         br = s2 * ar + c2 * xr;
@@ -272,148 +259,94 @@ __device__ void sweep_planes(double* __restrict__ hr, double* __restrict__ hi, i
         cr = ncr;
         ci = nci;
       }
-      if (k1 == k2) {
-        ar = R.na[k1];
-        dr = R.nb[k1];
+      if (k1 == k2 && f1) {
+        ar = na1;
+        dr = nb1;
         ai = di = br = bi = cr = ci = 0.0;
       }
-      hr[p1 * ldh + p2] = ar;
-      hi[p1 * ldh + p2] = ai;
-      hr[p1 * ldh + q2] = br;
-      hi[p1 * ldh + q2] = bi;
-      hr[q1 * ldh + p2] = cr;
-      hi[q1 * ldh + p2] = ci;
-      hr[q1 * ldh + q2] = dr;
-      hi[q1 * ldh + q2] = di;
+      if (f1 || f2) *any = 1;
+      orr[p1 * ldh + p2] = ar;
+      oi[p1 * ldh + p2] = ai;
+      orr[p1 * ldh + q2] = br;
+      oi[p1 * ldh + q2] = bi;
+      orr[q1 * ldh + p2] = cr;
+      oi[q1 * ldh + p2] = ci;
+      orr[q1 * ldh + q2] = dr;
+      oi[q1 * ldh + q2] = di;
     }
     for (int idx = t; idx < vrows * half; idx += nt) {
       const int row = (int)(((float)idx + 0.5f) * inv_half), k = idx - row * half;
-      if (!R.on[k]) continue;
       const int p = pt[2 * k], q = pt[2 * k + 1];
-      if (q >= vvalid) continue;
-      const double c = R.c[k], s = R.s[k], pr = R.pr[k], pi = -R.pi[k];
-      double apr, api, aqr, aqi;
-      if (VLDS) {
-        apr = vr[row * ldv + p];
-        api = vi[row * ldv + p];
-        aqr = vr[row * ldv + q];
-        aqi = vi[row * ldv + q];
-      } else {
-        z64 a = Vg[(size_t)row * ldvg + p], b = Vg[(size_t)row * ldvg + q];
-        apr = a.re;
-        api = a.im;
-        aqr = b.re;
-        aqi = b.im;
-      }
+      double c, sn, pr, pi, na, nb;
+      if (!rot_params(ir[p * ldh + p], ir[q * ldh + q], ir[p * ldh + q], ii[p * ldh + q], ja, c, sn, pr, pi, na, nb))
+        continue;
+      pi = -pi;
+      const double apr = vr[row * ldv + p], api = vi[row * ldv + p];
+      const double aqr = vr[row * ldv + q], aqi = vi[row * ldv + q];
       const double xr = pr * aqr - pi * aqi, xi = pr * aqi + pi * aqr;
-      const double npr = c * apr - s * xr, npi = c * api - s * xi;
-      const double nqr = s * apr + c * xr, nqi = s * api + c * xi;
-      if (VLDS) {
-        vr[row * ldv + p] = npr;
-        vi[row * ldv + p] = npi;
-        vr[row * ldv + q] = nqr;
-        vi[row * ldv + q] = nqi;
-      } else {
-        Vg[(size_t)row * ldvg + p] = z64{npr, npi};
-        Vg[(size_t)row * ldvg + q] = z64{nqr, nqi};
-      }
+      vr[row * ldv + p] = c * apr - sn * xr;
+      vi[row * ldv + p] = c * api - sn * xi;
+      vr[row * ldv + q] = sn * apr + c * xr;
+      vi[row * ldv + q] = sn * api + c * xi;
     }
     __syncthreads();
+    cur ^= 1;
+  }
+  return cur;
+}
+
+// Round-robin table for mp indices (mp - 1 steps of mp/2 pairs).
+__device__ void build_rr_table(unsigned char* tab, int mp) { build_pair_table(tab, mp); }
+
+// Inter-block table of a 2h-index pair problem: step s pairs k with h + (k + s) mod h.
+__device__ void build_ib_table(unsigned char* tab, int h) {
+  for (int e = threadIdx.x; e < h * h; e += blockDim.x) {
+    const int s = e / h, k = e - s * h;
+    tab[2 * e] = (unsigned char)k;
+    tab[2 * e + 1] = (unsigned char)(h + (k + s) % h);
   }
 }
 
-// LDS carve-up shared by the single-workgroup kernels: H planes, optional V planes, pair table,
-// rotation arrays.
-struct JacLds {
-  double *hr, *hi, *vr, *vi;
-  unsigned char* tab;
-  RotLds R;
-  int ldh;
-};
+constexpr int SMALL_LD = 33;  // plane leading dimension for sub-problems of up to 32 indices
 
-__host__ __device__ inline size_t jac_lds_bytes(int mp, bool vlds) {
-  const size_t ldh = mp + 1;
-  size_t b = 2 * (size_t)mp * ldh * sizeof(double);
-  if (vlds) b += 2 * (size_t)mp * ldh * sizeof(double);
-  b += (size_t)(mp - 1) * mp;                       // pair table
-  b = (b + 15) & ~size_t(15);
-  b += (size_t)(mp / 2) * (6 * sizeof(double) + sizeof(int)) + 64;
-  return b;
-}
-
-__device__ JacLds jac_carve(double* smem, int mp, bool vlds) {
-  JacLds L;
-  L.ldh = mp + 1;
-  const size_t plane = (size_t)mp * L.ldh;
-  L.hr = smem;
-  L.hi = smem + plane;
-  double* nxt = smem + 2 * plane;
-  if (vlds) {
-    L.vr = nxt;
-    L.vi = nxt + plane;
-    nxt += 2 * plane;
-  } else {
-    L.vr = L.vi = nullptr;
-  }
-  L.tab = reinterpret_cast<unsigned char*>(nxt);
-  size_t off = ((size_t)(mp - 1) * mp + 15) & ~size_t(15);
-  double* r = reinterpret_cast<double*>(L.tab + off);
-  const int half = mp / 2;
-  L.R.c = r;
-  L.R.s = r + half;
-  L.R.pr = r + 2 * half;
-  L.R.pi = r + 3 * half;
-  L.R.na = r + 4 * half;
-  L.R.nb = r + 5 * half;
-  L.R.on = reinterpret_cast<int*>(r + 6 * half);
-  return L;
-}
-
-// Single-workgroup Jacobi: G (m x m, m <= kSmallEig) -> U (m x m), lam (m).  For mp <= 64 the
-// eigenvector accumulator lives in LDS, otherwise in U directly.
+// Single-workgroup Jacobi: G (m x m, m <= kSmallEig = 32) -> U (m x m), lam (m), all in LDS.
 __global__ __launch_bounds__(256) void k_jacobi_small(const z64* __restrict__ G, int ldg_in, int m,
                                                       z64* __restrict__ U, int ldu, double* __restrict__ lam, int rel,
                                                       double tol, double skip_rel, int max_sweeps, DevStatus* st) {
-  extern __shared__ double smem[];
-  const int mp = m + (m & 1);
-  const bool vlds = mp <= 64;
-  JacLds L = jac_carve(smem, mp, vlds);
+  constexpr int PL = 32 * SMALL_LD;
+  __shared__ double h0r[PL], h0i[PL], h1r[PL], h1i[PL], vr[PL], vi[PL];
+  __shared__ unsigned char tab[31 * 32];
   __shared__ int any;
   __shared__ double trace;
-  const int t = threadIdx.x, nt = blockDim.x, ldh = L.ldh;
-  build_pair_table(L.tab, mp);
+  const int mp = m + (m & 1);
+  const int half = mp / 2;
+  const int t = threadIdx.x, nt = blockDim.x, ldh = SMALL_LD;
+  build_rr_table(tab, mp);
   for (int idx = t; idx < mp * mp; idx += nt) {
     const int i = idx / mp, j = idx - (idx / mp) * mp;
-    z64 v = (i < m && j < m) ? G[(size_t)i * ldg_in + j] : z64{0.0, 0.0};
-    L.hr[i * ldh + j] = v.re;
-    L.hi[i * ldh + j] = v.im;
-    if (vlds) {
-      L.vr[i * ldh + j] = (i == j) ? 1.0 : 0.0;
-      L.vi[i * ldh + j] = 0.0;
-    }
+    const z64 v = (i < m && j < m) ? G[(size_t)i * ldg_in + j] : z64{0.0, 0.0};
+    h0r[i * ldh + j] = v.re;
+    h0i[i * ldh + j] = v.im;
+    vr[i * ldh + j] = (i == j) ? 1.0 : 0.0;
+    vi[i * ldh + j] = 0.0;
   }
-  if (!vlds)
-    for (int idx = t; idx < m * m; idx += nt) {
-      const int i = idx / m, j = idx - (idx / m) * m;
-      U[(size_t)i * ldu + j] = (i == j) ? z64{1.0, 0.0} : z64{0.0, 0.0};
-    }
   __syncthreads();
   if (t == 0) {
     double tr = 0.0;
-    for (int i = 0; i < m; ++i) tr += fabs(L.hr[i * ldh + i]);
+    for (int i = 0; i < m; ++i) tr += fabs(h0r[i * ldh + i]);
     trace = tr;
   }
   __syncthreads();
   const JacobiArgs ja{tol * trace, tol, skip_rel * trace, rel};
-  int sweeps = 0;
+  int sweeps = 0, cur = 0;
   bool conv = false;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     if (t == 0) any = 0;
     __syncthreads();
-    if (vlds)
-      sweep_planes<true>(L.hr, L.hi, ldh, mp, L.tab, L.vr, L.vi, ldh, U, ldu, m, m, L.R, ja, &any);
-    else
-      sweep_planes<false>(L.hr, L.hi, ldh, mp, L.tab, L.vr, L.vi, ldh, U, ldu, m, m, L.R, ja, &any);
+    // an odd number of steps swaps the buffers; keep the live matrix in (h0)
+    const int res = jacobi_steps(cur ? h1r : h0r, cur ? h1i : h0i, cur ? h0r : h1r, cur ? h0i : h1i, ldh, half, tab,
+                                 mp - 1, vr, vi, ldh, mp, ja, &any);
+    cur ^= res;
     ++sweeps;
     __syncthreads();
     if (!any) {
@@ -421,12 +354,12 @@ __global__ __launch_bounds__(256) void k_jacobi_small(const z64* __restrict__ G,
       break;
     }
   }
-  for (int i = t; i < m; i += nt) lam[i] = L.hr[i * ldh + i];
-  if (vlds)
-    for (int idx = t; idx < m * m; idx += nt) {
-      const int i = idx / m, j = idx - (idx / m) * m;
-      U[(size_t)i * ldu + j] = z64{L.vr[i * ldh + j], L.vi[i * ldh + j]};
-    }
+  const double* fr = cur ? h1r : h0r;
+  for (int i = t; i < m; i += nt) lam[i] = fr[i * ldh + i];
+  for (int idx = t; idx < m * m; idx += nt) {
+    const int i = idx / m, j = idx - (idx / m) * m;
+    U[(size_t)i * ldu + j] = z64{vr[i * ldh + j], vi[i * ldh + j]};
+  }
   if (t == 0 && st) {
     st->converged = conv ? 1 : 0;
     st->sweeps = sweeps;
@@ -438,54 +371,58 @@ constexpr int BJ = kBlk;      // block size (16)
 constexpr int BJ2 = 2 * kBlk; // pair size (32)
 constexpr int SLD = BJ2 + 1;  // LDS leading dimension (plane layout)
 
-// Kernel A: pair k of step s runs one cyclic sweep on its 32x32 sub-problem and writes the
-// accumulated 32x32 rotation to V + k*32*32 (row-major) and a rotated flag.  A pair whose
-// off-diagonal entries are all below the threshold skips the sweep (flag 0).
+// Kernel A: pair k of outer step `step` solves its 32x32 sub-problem (blocks I, J) and writes the
+// accumulated rotation to V + k*32*32 (row-major) with a rotated flag.  The first step of an
+// outer sweep runs a full round-robin sweep over the 32 indices (covering the pairs inside each
+// block); later steps rotate only the 16 x 16 inter-block pairs.  Over one outer sweep every
+// index pair is visited once.
 __global__ __launch_bounds__(256) void k_jblock_solve(const z64* __restrict__ Gp, int mp, int nb, int step, double thr,
                                                       double tol, double skip, int rel, z64* __restrict__ Vout,
                                                       int* __restrict__ pair_flag, int* __restrict__ any_flag) {
-  extern __shared__ double smem[];
-  JacLds L = jac_carve(smem, BJ2, true);
+  constexpr int PL = BJ2 * SLD;
+  __shared__ double h0r[PL], h0i[PL], h1r[PL], h1i[PL], vr[PL], vi[PL];
+  __shared__ unsigned char tab[31 * 32];
   __shared__ int any, need;
-  const int k = blockIdx.x, t = threadIdx.x, nt = blockDim.x, ldh = L.ldh;
+  const int k = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
   int I, J;
   rr_pair(k, step, nb, I, J);
+  const bool full = (step == 0);
   if (t == 0) {
     any = 0;
     need = 0;
   }
-  build_pair_table(L.tab, BJ2);
-  __syncthreads();
+  if (full)
+    build_rr_table(tab, BJ2);
+  else
+    build_ib_table(tab, BJ);
   const JacobiArgs ja{thr, tol, skip, rel};
   for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
     const int i = idx / BJ2, j = idx % BJ2;
     const int gi = (i < BJ ? I * BJ + i : J * BJ + (i - BJ));
     const int gj = (j < BJ ? I * BJ + j : J * BJ + (j - BJ));
     const z64 v = Gp[(size_t)gi * mp + gj];
-    L.hr[i * ldh + j] = v.re;
-    L.hi[i * ldh + j] = v.im;
-    L.vr[i * ldh + j] = (i == j) ? 1.0 : 0.0;
-    L.vi[i * ldh + j] = 0.0;
+    h0r[i * SLD + j] = v.re;
+    h0i[i * SLD + j] = v.im;
+    vr[i * SLD + j] = (i == j) ? 1.0 : 0.0;
+    vi[i * SLD + j] = 0.0;
   }
   __syncthreads();
   for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
     const int i = idx / BJ2, j = idx % BJ2;
-    if (i < j) {
+    if (i < j && (full || (i < BJ && j >= BJ))) {
       double c, s, pr, pi, na, nb2;
-      if (rot_params(L.hr[i * ldh + i], L.hr[j * ldh + j], L.hr[i * ldh + j], L.hi[i * ldh + j], ja, c, s, pr, pi, na,
-                     nb2))
+      if (rot_params(h0r[i * SLD + i], h0r[j * SLD + j], h0r[i * SLD + j], h0i[i * SLD + j], ja, c, s, pr, pi, na, nb2))
         need = 1;
     }
   }
   __syncthreads();
   const int run = need;
   if (run) {
-    sweep_planes<true>(L.hr, L.hi, ldh, BJ2, L.tab, L.vr, L.vi, ldh, nullptr, 0, BJ2, BJ2, L.R, ja, &any);
-    __syncthreads();
+    jacobi_steps(h0r, h0i, h1r, h1i, SLD, BJ, tab, full ? BJ2 - 1 : BJ, vr, vi, SLD, BJ2, ja, &any);
     z64* vo = Vout + (size_t)k * BJ2 * BJ2;
     for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
       const int i = idx / BJ2, j = idx % BJ2;
-      vo[idx] = z64{L.vr[i * ldh + j], L.vi[i * ldh + j]};
+      vo[idx] = z64{vr[i * SLD + j], vi[i * SLD + j]};
     }
   }
   if (t == 0) {
@@ -826,9 +763,7 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   const double skip = rel ? 1e-34 : 0.0;
   const int max_sweeps = 40;
   if (m <= kSmallEig) {
-    const int mp = m + (m & 1);
-    const size_t lds = jac_lds_bytes(mp, mp <= 64);
-    hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(256), lds, s, G, ldg, m, U, ldu, lam, rel, tol, skip, max_sweeps,
+    hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(256), 0, s, G, ldg, m, U, ldu, lam, rel, tol, skip, max_sweeps,
                        st);
     GC_LAUNCH_CHECK();
     if (host_sweeps) *host_sweeps = -1;
@@ -848,7 +783,6 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   GC_HIP(hipMemcpyAsync(&trace, d_trace, sizeof(double), hipMemcpyDeviceToHost, s));
   GC_HIP(hipStreamSynchronize(s));
   const double thr = tol * trace, skipv = skip * trace;
-  const size_t lds_a = jac_lds_bytes(BJ2, true);
   const size_t lds_b = 4 * (size_t)BJ2 * SLD * sizeof(double);
   const int half = nb / 2;
   int sweeps = 0;
@@ -856,7 +790,7 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   for (int sw = 0; sw < max_sweeps; ++sw) {
     GC_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
     for (int step = 0; step < nb - 1; ++step) {
-      hipLaunchKernelGGL(k_jblock_solve, dim3(half), dim3(256), lds_a, s, Gp, mp, nb, step, thr, tol, skipv, rel, w.V,
+      hipLaunchKernelGGL(k_jblock_solve, dim3(half), dim3(256), 0, s, Gp, mp, nb, step, thr, tol, skipv, rel, w.V,
                          w.flags + 1, w.flags);
       GC_LAUNCH_CHECK();
       int tiles = half * half + (mp / BJ2) * half;
@@ -882,10 +816,6 @@ void linalg_set_attributes() {
   // Large dynamic LDS for the Jacobi kernels; a failure here only means the default limit
   // already allows it, so the sticky error state is cleared afterwards.
   const int lim = 160 * 1024;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_small), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lim);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_jblock_solve), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lim);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_jblock_apply), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lim);
   (void)hipGetLastError();

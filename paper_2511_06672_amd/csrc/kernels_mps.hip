@@ -6,6 +6,7 @@
 //    generates the rotated rows on the fly for large cuts,
 //  * FP64 selection (lowest index within tie_tol of the minimum) and the low-precision window,
 //  * dense helpers for the validation state vector.
+#include <algorithm>
 #include <cfloat>
 
 #include "kernels.h"
@@ -230,8 +231,6 @@ struct AccT<float> {
   typedef f4 type;
 };
 
-constexpr int ST = 64, SKC = 16, SPAD = 68;
-
 __device__ __forceinline__ void tile_pair(int idx, int nt, int& I, int& J) {
   int i = 0, rem = idx;
   while (rem >= nt - i) {
@@ -242,75 +241,118 @@ __device__ __forceinline__ void tile_pair(int idx, int nt, int& I, int& J) {
   J = i + rem;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_score_tiled(int d, int chil, int chir, const z64* __restrict__ theta,
-                                                     const z64* __restrict__ q64, const c32* __restrict__ q32,
-                                                     const int* __restrict__ list, const int* __restrict__ nlimit,
-                                                     int ntp, double* __restrict__ partial) {
-  typedef typename AccT<T>::type acc_t;
-  const int slot = blockIdx.y;
-  if (nlimit && slot >= *nlimit) return;
+// Rotated two-site matrices N_c (m x k, row-major) for a chunk of candidates.  One thread per
+// (a, b) loads Theta(a, :, :, b) once and writes the d^2 entries (Q_c Theta)(a, s1', s2', b) to
+// their (row, col) positions: rows (a s1'), cols (s2' b) when chil*d <= d*chir, else transposed.
+template <typename T, int DD>
+__global__ __launch_bounds__(256) void k_gen_rotated(int d_rt, int chil, int chir, const z64* __restrict__ theta,
+                                                     const cx<T>* __restrict__ qall, const int* __restrict__ list,
+                                                     int c0, int cnt, const int* __restrict__ nlimit,
+                                                     cx<T>* __restrict__ out, size_t stride) {
+  // DD > 0: qudit dimension fixed at compile time (the d^2-vector stays in registers)
+  const int d = DD > 0 ? DD : d_rt;
+  constexpr int VMAX = DD > 0 ? DD * DD : kMaxD * kMaxD;
+  const int ls = blockIdx.y;
+  const int slot = c0 + ls;
+  if (ls >= cnt || (nlimit && slot >= *nlimit)) return;
   const int c = list ? list[slot] : slot;
   const bool rows_first = chil * d <= d * chir;
-  const int m = rows_first ? chil * d : d * chir;
   const int k = rows_first ? d * chir : chil * d;
-  const int nt = (m + ST - 1) / ST;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)chil * chir) return;
+  // rows_first: b fastest (contiguous columns s2'*chir + b); otherwise a fastest
+  int a, b;
+  if (rows_first) {
+    a = (int)(idx / chir);
+    b = (int)(idx % chir);
+  } else {
+    b = (int)(idx / chil);
+    a = (int)(idx % chil);
+  }
+  const int D2 = d * d;
+  const cx<T>* q = qall + (size_t)c * D2 * D2;
+  cx<T> v[VMAX];
+  const z64* th = theta + (size_t)a * D2 * chir + b;
+#pragma unroll
+  for (int x = 0; x < VMAX; ++x) {
+    if (x >= D2) break;
+    const z64 tv = th[(size_t)x * chir];
+    v[x] = cx<T>{T(tv.re), T(tv.im)};
+  }
+  cx<T>* o = out + (size_t)ls * stride;
+  for (int y = 0; y < D2; ++y) {
+    const int s1p = y / d, s2p = y - s1p * d;
+    cx<T> acc = {T(0), T(0)};
+#pragma unroll
+    for (int x = 0; x < VMAX; ++x) {
+      if (x >= D2) break;
+      acc = cadd(acc, cmul(q[y * D2 + x], v[x]));
+    }
+    const size_t row = rows_first ? (size_t)a * d + s1p : (size_t)s2p * chir + b;
+    const size_t col = rows_first ? (size_t)s2p * chir + b : (size_t)a * d + s1p;
+    o[row * k + col] = acc;
+  }
+}
+
+// Purity tiles: for candidate slot `ls` of the chunk, tile (I, J), I <= J, of rho = N N^H over the
+// k columns, on MFMA (16x16x4, FP32 or FP64 accumulate).  Each of the four waves owns a quadrant
+// of BL x BL 16x16 blocks (TT = 32 * BL).  The epilogue writes sum |rho_tile|^2 (doubled off the
+// diagonal) and the tile's trace to partial[slot][tile].
+template <typename T, int BL>
+__global__ __launch_bounds__(256) void k_gram_purity(int m, int k, const cx<T>* __restrict__ nbase, size_t stride,
+                                                     int c0, int cnt, const int* __restrict__ nlimit, int ntp,
+                                                     double* __restrict__ partial) {
+  typedef typename AccT<T>::type acc_t;
+  constexpr int TT = 32 * BL, KC = 16, PAD = TT + 4;
+  const int ls = blockIdx.y;
+  const int slot = c0 + ls;
+  if (ls >= cnt || (nlimit && slot >= *nlimit)) return;
+  const cx<T>* N = nbase + (size_t)ls * stride;
+  const int nt = (m + TT - 1) / TT;
   int I, J;
   tile_pair(blockIdx.x, nt, I, J);
-  const int D4 = d * d * d * d;
-  __shared__ cx<T> qs[kMaxD * kMaxD * kMaxD * kMaxD];
-  __shared__ T As[2][SKC][SPAD];
-  __shared__ T Bs[2][SKC][SPAD];
+  __shared__ T As[2][KC][PAD];
+  __shared__ T Bs[2][KC][PAD];
   __shared__ double red[256];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  const cx<T>* qall = qsel<T>(q64, q32);
-  for (int i = t; i < D4; i += 256) qs[i] = qall[(size_t)c * D4 + i];
-  __syncthreads();
-  acc_t accr[2][2], acci[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+  const int wr = (w >> 1) * (TT / 2), wc = (w & 1) * (TT / 2);
+  acc_t accr[BL][BL], acci[BL][BL];
+  for (int i = 0; i < BL; ++i)
+    for (int j = 0; j < BL; ++j)
       for (int q = 0; q < 4; ++q) {
         accr[i][j][q] = T(0);
         acci[i][j][q] = T(0);
       }
-  const int r0 = I * ST, c0 = J * ST;
-  for (int k0 = 0; k0 < k; k0 += SKC) {
+  const int r0 = I * TT, q0 = J * TT;
+  for (int k0 = 0; k0 < k; k0 += KC) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int e = t + 256 * u;
-      int row, kk;
-      if (rows_first) {
-        row = e >> 4;
-        kk = e & 15;
-      } else {
-        row = e & 63;
-        kk = e >> 6;
-      }
-      int col = k0 + kk;
+    for (int u = 0; u < TT * KC / 256; ++u) {
+      const int e = t + 256 * u;
+      const int row = e >> 4, kk = e & 15;
+      const int col = k0 + kk;
       cx<T> va = {T(0), T(0)}, vb = {T(0), T(0)};
       if (col < k) {
-        if (r0 + row < m) va = nelem<T>(d, chil, chir, rows_first, theta, qs, r0 + row, col);
-        if (c0 + row < m) vb = nelem<T>(d, chil, chir, rows_first, theta, qs, c0 + row, col);
+        if (r0 + row < m) va = N[(size_t)(r0 + row) * k + col];
+        if (q0 + row < m) vb = N[(size_t)(q0 + row) * k + col];
       }
       As[0][kk][row] = va.re;
       As[1][kk][row] = va.im;
-      Bs[0][kk][row] = vb.re;     // B operand = conj(N[J rows])^T
+      Bs[0][kk][row] = vb.re;
       Bs[1][kk][row] = -vb.im;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < SKC; kk += 4) {
+    for (int kk = 0; kk < KC; kk += 4) {
       const int ka = kk + (lane >> 4);
-      T ar[2], ai[2], br[2], bi[2];
-      for (int i = 0; i < 2; ++i) {
+      T ar[BL], ai[BL], br[BL], bi[BL];
+      for (int i = 0; i < BL; ++i) {
         ar[i] = As[0][ka][wr + i * 16 + (lane & 15)];
         ai[i] = As[1][ka][wr + i * 16 + (lane & 15)];
         br[i] = Bs[0][ka][wc + i * 16 + (lane & 15)];
         bi[i] = Bs[1][ka][wc + i * 16 + (lane & 15)];
       }
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {
+      for (int i = 0; i < BL; ++i)
+        for (int j = 0; j < BL; ++j) {
           accr[i][j] = mfma_t(ar[i], br[j], accr[i][j]);
           accr[i][j] = mfma_t(-ai[i], bi[j], accr[i][j]);
           acci[i][j] = mfma_t(ar[i], bi[j], acci[i][j]);
@@ -321,13 +363,13 @@ __global__ __launch_bounds__(256) void k_score_tiled(int d, int chil, int chir, 
   }
   double pur = 0.0, tr = 0.0;
   const double wgt = (I == J) ? 1.0 : 2.0;
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+  for (int i = 0; i < BL; ++i)
+    for (int j = 0; j < BL; ++j)
       for (int q = 0; q < 4; ++q) {
-        int row = r0 + wr + i * 16 + mfma_row<T>(lane, q);
-        int col = c0 + wc + j * 16 + (lane & 15);
+        const int row = r0 + wr + i * 16 + mfma_row<T>(lane, q);
+        const int col = q0 + wc + j * 16 + (lane & 15);
         if (row < m && col < m) {
-          double re = (double)accr[i][j][q], im = (double)acci[i][j][q];
+          const double re = (double)accr[i][j][q], im = (double)acci[i][j][q];
           pur += wgt * (re * re + im * im);
           if (I == J && row == col) tr += re;
         }
@@ -544,9 +586,13 @@ void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* s
 }
 
 void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64* theta, const z64* q64, const c32* q32,
-                  const int* list, int count, const int* nlimit, double* s2, double* partial, size_t partial_cap) {
+                  const int* list, int count, const int* nlimit, double* s2, double* partial, size_t partial_cap,
+                  void* nbuf, size_t nbuf_bytes, hipEvent_t* evs, int evcap, int* evused) {
+  if (evused) *evused = 0;
   if (count <= 0) return;
-  const int m = (chil * d <= d * chir) ? chil * d : d * chir;
+  const bool rows_first = chil * d <= d * chir;
+  const int m = rows_first ? chil * d : d * chir;
+  const int k = rows_first ? d * chir : chil * d;
   if (m <= SMALL_M) {
     if (prec == GCAMPS_SCORE_FP64)
       hipLaunchKernelGGL(k_score_small<double>, dim3(count), dim3(SMALL_THREADS), 0, s, d, chil, chir, theta, q64,
@@ -557,17 +603,53 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
     GC_LAUNCH_CHECK();
     return;
   }
-  const int nt = (m + ST - 1) / ST;
+  const int TT = (prec == GCAMPS_SCORE_FP64) ? 64 : 128;
+  const int nt = (m + TT - 1) / TT;
   const int ntp = nt * (nt + 1) / 2;
   GC_CHECK((size_t)count * ntp * 2 <= partial_cap, GCAMPS_ECAPACITY, "scoring partial buffer too small");
-  dim3 grid(ntp, count);
-  if (prec == GCAMPS_SCORE_FP64)
-    hipLaunchKernelGGL(k_score_tiled<double>, grid, dim3(256), 0, s, d, chil, chir, theta, q64, q32, list, nlimit,
-                       ntp, partial);
-  else
-    hipLaunchKernelGGL(k_score_tiled<float>, grid, dim3(256), 0, s, d, chil, chir, theta, q64, q32, list, nlimit, ntp,
-                       partial);
-  GC_LAUNCH_CHECK();
+  const size_t elem = (prec == GCAMPS_SCORE_FP64) ? sizeof(z64) : sizeof(c32);
+  const size_t stride = (size_t)m * k;
+  const int chunk = (int)std::min<size_t>((size_t)count, nbuf_bytes / (stride * elem));
+  GC_CHECK(chunk >= 1, GCAMPS_ECAPACITY, "rotated-matrix buffer too small");
+  const dim3 ggen(blocks_for((size_t)chil * chir, 256), chunk);
+  for (int c0 = 0; c0 < count; c0 += chunk) {
+    const int cnt = std::min(chunk, count - c0);
+    const dim3 gg(ggen.x, cnt), gp(ntp, cnt);
+    const int ev = (evs && evused && 2 * (*evused) + 1 < evcap) ? 2 * (*evused) : -1;
+    if (prec == GCAMPS_SCORE_FP64) {
+      z64* nb = reinterpret_cast<z64*>(nbuf);
+      if (d == 3)
+        hipLaunchKernelGGL((k_gen_rotated<double, 3>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
+                           nlimit, nb, stride);
+      else if (d == 2)
+        hipLaunchKernelGGL((k_gen_rotated<double, 2>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
+                           nlimit, nb, stride);
+      else
+        hipLaunchKernelGGL((k_gen_rotated<double, 0>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
+                           nlimit, nb, stride);
+      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
+      hipLaunchKernelGGL((k_gram_purity<double, 2>), gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
+                         partial);
+      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
+    } else {
+      c32* nb = reinterpret_cast<c32*>(nbuf);
+      if (d == 3)
+        hipLaunchKernelGGL((k_gen_rotated<float, 3>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
+                           nlimit, nb, stride);
+      else if (d == 2)
+        hipLaunchKernelGGL((k_gen_rotated<float, 2>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
+                           nlimit, nb, stride);
+      else
+        hipLaunchKernelGGL((k_gen_rotated<float, 0>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
+                           nlimit, nb, stride);
+      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
+      hipLaunchKernelGGL((k_gram_purity<float, 4>), gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
+                         partial);
+      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
+    }
+    GC_LAUNCH_CHECK();
+    if (ev >= 0) ++(*evused);
+  }
   hipLaunchKernelGGL(k_score_reduce, dim3(blocks_for(count, 128)), dim3(128), 0, s, ntp, nlimit, count, partial, s2);
   GC_LAUNCH_CHECK();
 }
