@@ -188,6 +188,66 @@ int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap,
  * centre tensor (identity kept), [15] reserved (0). */
 int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[16]);
 
+/* ---------------------------------------------------------------------------
+ * Batched independent circuits.
+ *
+ * Many circuits, each with its own configuration, are simulated concurrently
+ * (the method of §2-§3 applied to each circuit; circuits never interact).
+ * `lanes` host threads each own one HIP stream (default priority, created and
+ * destroyed by the call) and one slice of the caller's workspace; they take
+ * circuits from a shared queue ordered by estimated cost, largest first.  The
+ * bonds of one circuit stay sequential; kernels of different circuits overlap on
+ * the GPU.  Each circuit runs through gcamps_init and the single-state calls
+ * above, so its results are bit-identical to running it alone with the same
+ * configuration and candidate set.
+ * ------------------------------------------------------------------------- */
+enum { GCAMPS_OP_CLIFFORD_LAYER = 0, GCAMPS_OP_PHASE = 1 };
+
+typedef struct {
+  int32_t kind;             /* GCAMPS_OP_* */
+  int32_t count;            /* CLIFFORD_LAYER: number of words (disjoint pairs); PHASE: unused */
+  const int32_t* sites;     /* CLIFFORD_LAYER: `count` pair sites; PHASE: one site */
+  const gcamps_word* words; /* CLIFFORD_LAYER: `count` words; PHASE: unused (NULL) */
+  const double* phi;        /* PHASE: d angles of diag(e^{i phi_j}); CLIFFORD_LAYER: unused */
+} gcamps_op;
+
+typedef struct {
+  gcamps_config cfg;     /* per circuit; cfg.d must equal the candidate set's d */
+  const gcamps_op* ops;  /* applied in order, as gcamps_apply_clifford_layer /
+                            gcamps_apply_phase_rotation would apply them */
+  int64_t n_ops;
+  /* Outputs: caller-owned host memory, each may be NULL. */
+  int32_t* status;       /* GCAMPS_OK or the code of the call that failed */
+  double* fidelity;      /* 1 value: the fidelity estimate after the circuit */
+  int32_t* bond_dims;    /* n - 1 values */
+  double* z_expect;      /* 2n values: <psi|Z_j|psi> for j = 0..n-1 as (re, im) */
+  int32_t* choices;      /* choice-log quadruples (gate, sweep, bond, c*), at most choices_cap */
+  int64_t choices_cap;
+  int64_t* choices_len;  /* total number of quadruples */
+} gcamps_batch_item;
+
+/* Device workspace for gcamps_batch_run: min(lanes, count) slices, each the
+ * largest gcamps_workspace_bytes() over the items (rounded up to 256 bytes).
+ * Errors: EINVAL (null pointers, lanes outside [1, 64], malformed ops, bad config),
+ * EUNSUPPORTED (non-prime d). */
+int32_t gcamps_batch_workspace_bytes(const gcamps_batch_item* items, int32_t count, int32_t lanes,
+                                     size_t* bytes);
+
+/* Run `count` circuits on `lanes` concurrent lanes of the current HIP device.
+ * set: candidate set attached to every circuit (may be NULL: no disentangling).
+ * dev_workspace: 256-byte aligned device memory of gcamps_batch_workspace_bytes()
+ * bytes, borrowed for the call.  Every item is attempted; each item's status is
+ * written when non-NULL.  Returns GCAMPS_OK, or the code of the failed item with
+ * the lowest index (gcamps_last_error names it).  stats (16 doubles, may be NULL):
+ * [0] circuits completed, [1] non-Clifford gates applied, [2] wall time in ms,
+ * [3] summed lane busy time in ms, [4] lanes used, [5] summed full-set scoring
+ * kernel time in ms, [6] bonds scored, [7] Gram-purity kernel launches, [8] their
+ * summed kernel time in ms, [9] their algorithmic flops (as gcamps_get_stats
+ * [11]-[13], summed over circuits), [10]-[15] reserved (0).
+ * Errors: EINVAL, EUNSUPPORTED, EWORKSPACE, ECAPACITY, ENUMERIC, EDEVICE. */
+int32_t gcamps_batch_run(const gcamps_batch_item* items, int32_t count, const gcamps_candset* set,
+                         int32_t lanes, void* dev_workspace, size_t bytes, double stats[16]);
+
 /* Thread-local message for the last failed call on this thread. */
 const char* gcamps_last_error(void);
 

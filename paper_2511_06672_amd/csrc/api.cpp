@@ -9,7 +9,9 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <atomic>
 #include <memory>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -22,7 +24,7 @@ void linalg_set_attributes();
 namespace {
 
 thread_local std::string g_last_error;
-uint64_t g_uid = 1;
+std::atomic<uint64_t> g_uid{1};
 
 bool is_prime(int d) {
   if (d < 2) return false;
@@ -470,11 +472,8 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
     GC_CHECK(((uintptr_t)dev_workspace & 255) == 0, GCAMPS_EINVAL, "workspace must be 256-byte aligned");
     Layout lay = make_layout(*cfg);
     GC_CHECK(bytes >= lay.total, GCAMPS_EWORKSPACE, "workspace smaller than gcamps_workspace_bytes()");
-    static bool attrs_done = false;
-    if (!attrs_done) {
-      linalg_set_attributes();
-      attrs_done = true;
-    }
+    static std::once_flag attrs_once;
+    std::call_once(attrs_once, linalg_set_attributes);
     auto c = std::make_unique<gcamps_ctx>();
     c->cfg = *cfg;
     c->lay = lay;
@@ -613,7 +612,7 @@ int32_t gcamps_candset_create(int32_t d, const gcamps_word* words, int32_t count
     s->d = d;
     s->count = count;
     for (int i = 0; i < count; ++i) s->words.push_back(compile_word(d, words[i]));
-    s->uid = g_uid++;
+    s->uid = g_uid.fetch_add(1);
     *out = s.release();
   });
 }

@@ -27,7 +27,7 @@ SYMBOLS = [
     "gcamps_candset_destroy", "gcamps_set_candset", "gcamps_disentangle", "gcamps_expectation",
     "gcamps_statevector", "gcamps_amplitude", "gcamps_get_tableau", "gcamps_get_bond_dims",
     "gcamps_get_fidelity", "gcamps_get_choice_log", "gcamps_get_site", "gcamps_get_stats",
-    "gcamps_last_error",
+    "gcamps_batch_workspace_bytes", "gcamps_batch_run", "gcamps_last_error",
 ]
 
 
@@ -46,6 +46,22 @@ class Config(C.Structure):
 
 class CWord(C.Structure):
     _fields_ = [("len", C.c_int32), ("gens", C.POINTER(C.c_uint8)), ("weyl", C.c_int32 * 4)]
+
+
+OP_CLIFFORD_LAYER, OP_PHASE = 0, 1
+
+
+class COp(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("count", C.c_int32), ("sites", C.POINTER(C.c_int32)),
+                ("words", C.POINTER(CWord)), ("phi", C.POINTER(C.c_double))]
+
+
+class CBatchItem(C.Structure):
+    _fields_ = [("cfg", Config), ("ops", C.POINTER(COp)), ("n_ops", C.c_int64),
+                ("status", C.POINTER(C.c_int32)), ("fidelity", C.POINTER(C.c_double)),
+                ("bond_dims", C.POINTER(C.c_int32)), ("z_expect", C.POINTER(C.c_double)),
+                ("choices", C.POINTER(C.c_int32)), ("choices_cap", C.c_int64),
+                ("choices_len", C.POINTER(C.c_int64))]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -74,6 +90,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gcamps_get_choice_log": [P, C.POINTER(I32), I64, C.POINTER(I64)],
         "gcamps_get_site": [P, I32, C.POINTER(D), I64, C.POINTER(I32)],
         "gcamps_get_stats": [P, C.POINTER(D)],
+        "gcamps_batch_workspace_bytes": [C.POINTER(CBatchItem), I32, I32, C.POINTER(SZ)],
+        "gcamps_batch_run": [C.POINTER(CBatchItem), I32, P, I32, P, SZ, C.POINTER(D)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -272,3 +290,91 @@ def run_circuit(state: State, circuit, phases_override=None):
                 phi = phases_override[ph.param]
             state.apply_phase_rotation(ph.site, phi)
     return state
+
+
+def _circuit_ops(circuit, keep: list, phases_override=None):
+    """Marshal a workload Circuit into a gcamps_op array (buffers kept alive in `keep`)."""
+    ops = []
+    for layer in circuit.layers:
+        if layer.bricks:
+            arr, kw = _words([b.word for b in layer.bricks])
+            sites = (C.c_int32 * len(layer.bricks))(*[b.site for b in layer.bricks])
+            keep.extend([arr, kw, sites])
+            ops.append((OP_CLIFFORD_LAYER, len(layer.bricks), sites, arr, None))
+        for ph in layer.phases:
+            phi = ph.phi
+            if phases_override is not None and ph.param >= 0:
+                phi = phases_override[ph.param]
+            site = (C.c_int32 * 1)(ph.site)
+            a = (C.c_double * circuit.d)(*phi)
+            keep.extend([site, a])
+            ops.append((OP_PHASE, 1, site, None, a))
+    out = (COp * max(1, len(ops)))()
+    for i, (kind, cnt, sites, words, phi) in enumerate(ops):
+        out[i].kind = kind
+        out[i].count = cnt
+        out[i].sites = C.cast(sites, C.POINTER(C.c_int32))
+        out[i].words = C.cast(words, C.POINTER(CWord)) if words is not None else None
+        out[i].phi = C.cast(phi, C.POINTER(C.c_double)) if phi is not None else None
+    keep.append(out)
+    return out, len(ops)
+
+
+def batch_run(circuits, cfgs, candset: Optional[CandSet] = None, lanes: int = 4,
+              device: str = "cuda:0"):
+    """gcamps_batch_run over workload Circuits with per-circuit Configs.
+
+    Returns (results, stats): one dict per circuit (status, fidelity, bond_dims,
+    z_expect, choices) and the batch statistics.
+    """
+    import torch
+    assert len(circuits) == len(cfgs) and circuits
+    keep: list = []
+    count = len(circuits)
+    items = (CBatchItem * count)()
+    outs = []
+    for i, (c, cfg) in enumerate(zip(circuits, cfgs)):
+        ops, nops = _circuit_ops(c, keep)
+        status = (C.c_int32 * 1)(-99)
+        fid = (C.c_double * 1)()
+        bonds = (C.c_int32 * (c.n - 1))()
+        zexp = (C.c_double * (2 * c.n))()
+        cap = max(1, c.n_phase_gates * max(1, cfg.max_sweeps) * (c.n - 1))
+        ch = (C.c_int32 * (4 * cap))()
+        chlen = (C.c_int64 * 1)()
+        keep.extend([status, fid, bonds, zexp, ch, chlen])
+        it = items[i]
+        it.cfg = cfg
+        it.ops = ops
+        it.n_ops = nops
+        it.status = C.cast(status, C.POINTER(C.c_int32))
+        it.fidelity = C.cast(fid, C.POINTER(C.c_double))
+        it.bond_dims = C.cast(bonds, C.POINTER(C.c_int32))
+        it.z_expect = C.cast(zexp, C.POINTER(C.c_double))
+        it.choices = C.cast(ch, C.POINTER(C.c_int32))
+        it.choices_cap = cap
+        it.choices_len = C.cast(chlen, C.POINTER(C.c_int64))
+        outs.append((status, fid, bonds, zexp, ch, chlen, c.n))
+    nbytes = C.c_size_t(0)
+    _check(lib().gcamps_batch_workspace_bytes(items, count, lanes, C.byref(nbytes)))
+    dev = torch.device(device)
+    with torch.cuda.device(dev):
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        aligned = (ws.data_ptr() + 255) & ~255
+        torch.cuda.synchronize(dev)
+        st = (C.c_double * 16)()
+        rc = lib().gcamps_batch_run(items, count, candset.handle if candset else None, lanes,
+                                    C.c_void_p(aligned), nbytes.value, st)
+    results = []
+    for status, fid, bonds, zexp, ch, chlen, n in outs:
+        z = np.frombuffer(zexp, dtype=np.float64)
+        ln = min(chlen[0], len(ch) // 4)
+        results.append({"status": status[0], "fidelity": fid[0], "bond_dims": list(bonds),
+                        "z_expect": z[0::2] + 1j * z[1::2],
+                        "choices": np.frombuffer(ch, dtype=np.int32)[:4 * ln].reshape(-1, 4).copy(),
+                        "choices_len": chlen[0]})
+    del ws
+    _check(rc)
+    keys = ["circuits", "gates", "wall_ms", "busy_ms", "lanes", "score_ms", "bonds", "tiled_launches",
+            "tiled_ms", "tiled_flops"]
+    return results, dict(zip(keys, list(st)))

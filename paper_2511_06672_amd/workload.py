@@ -44,6 +44,7 @@ STREAM_CIRCUIT = 1
 STREAM_PHASE_POS = 2
 STREAM_CANDIDATES = 3
 STREAM_THETA = 4
+STREAM_BATCH = 5
 
 
 class SplitMix64:
@@ -220,6 +221,39 @@ def workload(name: str, n: int | None = None) -> Workload:
                               parametrised=True)
         return Workload(name, c, candidate_words(3, 512, seed), chi_max=256, cutoff=1e-10)
     raise KeyError(name)
+
+
+@dataclass
+class BatchWorkload:
+    name: str
+    circuits: List[Circuit]
+    candidates: List[Word]
+    chi_max: int
+    cutoff: float
+    max_sweeps: int = 2
+
+    @property
+    def n_phase_gates(self) -> int:
+        return sum(c.n_phase_gates for c in self.circuits)
+
+
+def batch_workload(count: int = 256, seed: int = 3000, n_range: Tuple[int, int] = (8, 48),
+                   t_range: Tuple[int, int] = (4, 60), chi_max: int = 128, cutoff: float = 1e-10,
+                   n_candidates: int = 512, name: str = "batch_d3") -> BatchWorkload:
+    """Independent qutrit circuits of uneven size.
+
+    Circuit i draws n_i ~ U{n_lo..n_hi} and T_i ~ U{t_lo..t_hi} from the batch stream
+    of ``seed``, has 2 n_i brickwork layers and T_i T gates at uniform (layer, site),
+    and is generated with seed ``seed + 1 + i``.  One candidate set (seed ``seed``) is
+    shared by every circuit.
+    """
+    rng = substream(seed, STREAM_BATCH)
+    circuits = []
+    for i in range(count):
+        n = n_range[0] + rng.below(n_range[1] - n_range[0] + 1)
+        t = t_range[0] + rng.below(t_range[1] - t_range[0] + 1)
+        circuits.append(brickwork_circuit(3, n, 2 * n, t, seed + 1 + i, one_per_layer=False))
+    return BatchWorkload(name, circuits, candidate_words(3, n_candidates, seed), chi_max, cutoff)
 
 
 def circuit_to_json(c: Circuit) -> dict:

@@ -6,7 +6,7 @@ Calls only ``oracle/`` (and the seeded workload generator).  The JSON is rewritt
 after every non-Clifford gate, so an interrupted run still leaves a valid prefix:
 ``gates_done`` says how many gates are covered.
 
-    OPENBLAS_NUM_THREADS=4 python tests/golden/make_headline_reference.py [n]
+    OPENBLAS_NUM_THREADS=4 python tests/golden/make_headline_reference.py [n] [out_dir]
 """
 import hashlib
 import json
@@ -33,7 +33,8 @@ def main():
     n = int(sys.argv[1]) if len(sys.argv) > 1 else 32
     wl = workload("headline_d3_n32", n=None if n == 32 else n)
     c = wl.circuit
-    out_path = os.path.join(HERE, f"headline_d3_n{n}_oracle.json")
+    out_dir = sys.argv[2] if len(sys.argv) > 2 else HERE
+    out_path = os.path.join(out_dir, f"headline_d3_n{n}_oracle.json")
     g = Gcamps(c.d, c.n, Config(chi_max=wl.chi_max, cutoff=wl.cutoff, max_sweeps=wl.max_sweeps),
                wl.candidates)
     rec = {"workload": wl.name, "d": c.d, "n": c.n, "layers": len(c.layers), "chi_max": wl.chi_max,

@@ -61,3 +61,66 @@ def test_init_rejects_small_workspace_without_device_work():
     assert code == -3                                               # EWORKSPACE
     code = g.lib().gcamps_init(C.byref(cfg), C.c_void_p(257), 1 << 40, None, C.byref(h))
     assert code == -1                                               # misaligned workspace
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes and offsets."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = {
+        "gcamps_config": (g.Config, ["d", "n", "chi_max", "cutoff", "score_prec", "near_tie", "tie_tol",
+                                     "max_sweeps", "auto_disentangle", "max_candidates"]),
+        "gcamps_word": (g.CWord, ["len", "gens", "weyl"]),
+        "gcamps_op": (g.COp, ["kind", "count", "sites", "words", "phi"]),
+        "gcamps_batch_item": (g.CBatchItem, ["cfg", "ops", "n_ops", "status", "fidelity", "bond_dims",
+                                             "z_expect", "choices", "choices_cap", "choices_len"]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gcamps.h"', "int main(void) {"]
+    for cname, (_, names) in fields.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f in names:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    expect = []
+    for cname, (cls, names) in fields.items():
+        expect.append(C.sizeof(cls))
+        expect.extend(getattr(cls, f).offset for f in names)
+    assert vals == expect
+
+
+def test_batch_validation_without_device_work():
+    import ctypes as C
+    from paper_2511_06672_amd.workload import brickwork_circuit
+    c = brickwork_circuit(3, 5, 4, 2, 11, one_per_layer=False)
+    keep = []
+    ops, nops = g._circuit_ops(c, keep)
+    items = (g.CBatchItem * 2)()
+    for it in items:
+        it.cfg = g.make_config(3, 5, 9, 0.0)
+        it.ops = ops
+        it.n_ops = nops
+    b1, b2 = C.c_size_t(0), C.c_size_t(0)
+    assert g.lib().gcamps_batch_workspace_bytes(items, 2, 1, C.byref(b1)) == 0
+    assert g.lib().gcamps_batch_workspace_bytes(items, 2, 4, C.byref(b2)) == 0
+    assert b2.value == 2 * b1.value                                  # min(lanes, count) slices
+    assert b1.value >= g.workspace_bytes(items[0].cfg)
+    assert g.lib().gcamps_batch_workspace_bytes(items, 2, 0, C.byref(b1)) == -1     # lanes < 1
+    assert g.lib().gcamps_batch_workspace_bytes(items, 0, 1, C.byref(b1)) == -1     # empty batch
+    items[1].cfg = g.make_config(4, 5, 9, 0.0)
+    assert g.lib().gcamps_batch_workspace_bytes(items, 2, 1, C.byref(b1)) == -2     # non-prime d
+    items[1].cfg = g.make_config(3, 5, 9, 0.0)
+    ops[0].kind = 7
+    assert g.lib().gcamps_batch_workspace_bytes(items, 2, 1, C.byref(b1)) == -1     # unknown op
+    assert "unknown kind" in g.lib().gcamps_last_error().decode()
+    ops[0].kind = g.OP_CLIFFORD_LAYER
+    assert g.lib().gcamps_batch_run(items, 2, None, 1, C.c_void_p(256), 16, None) == -3  # EWORKSPACE
+    assert g.lib().gcamps_batch_run(items, 2, None, 1, C.c_void_p(257), 1 << 40, None) == -1
