@@ -91,8 +91,15 @@ class ChoiceEntry:
 
 
 class Gcamps:
-    def __init__(self, d: int, n: int, cfg: Config, candidates: Sequence = ()):
+    def __init__(self, d: int, n: int, cfg: Config, candidates: Sequence = (), frozen=None):
+        """``frozen`` = (choices, ranks) replays a recorded run: the disentangler takes the
+        recorded choices in order (no scoring) and every truncating split keeps the
+        recorded rank.  The rank log lists the kept rank of every truncating split
+        (compression splits, then disentangler splits, in execution order)."""
         self.d, self.n, self.cfg = d, n, cfg
+        self.rank_log: List[int] = []
+        self._frozen_choices = list(frozen[0]) if frozen is not None else None
+        self._frozen_ranks = list(frozen[1]) if frozen is not None else None
         self.tab = Tableau(d, n)
         self.mps = MPS.product_zero(d, n)
         self.f_est = 1.0
@@ -125,7 +132,12 @@ class Gcamps:
         self.mps.move_centre(l)
         self.mps.apply_block_mpo(l, r, ops, coeff)
         if r > l:
-            epss, flags = self.mps.truncate_sweep_left(l, r, self.cfg.cutoff, self.cfg.chi_max)
+            force = None
+            if self._frozen_ranks is not None:
+                force = [self._frozen_ranks.pop(0) for _ in range(r - l)]
+            epss, flags = self.mps.truncate_sweep_left(l, r, self.cfg.cutoff, self.cfg.chi_max,
+                                                       force_ks=force)
+            self.rank_log.extend(self.mps.last_ks)
             for e in epss:
                 self.f_est *= (1.0 - e)
             self.flags += sum(flags)
@@ -157,8 +169,10 @@ class Gcamps:
             for i in bonds:
                 self.mps.move_centre(i if left_to_right else i + 1)
                 th = self.mps.theta(i)
-                s2 = self.scores(th)
-                c = self.select(s2)
+                if self._frozen_choices is not None:
+                    c = self._frozen_choices.pop(0)
+                else:
+                    c = self.select(self.scores(th))
                 self.choice_log.append(ChoiceEntry(self.gate_count - 1, sweep, i, c))
                 if c != 0:
                     w = self.candidates[c]
@@ -168,8 +182,10 @@ class Gcamps:
                     self.tab.right_multiply_dagger(i, w.gens, w.weyl)
                     self.record.append(("Q", i, tuple(w.gens), tuple(w.weyl)))
                     changed += 1
-                eps, flagged, _ = self.mps.split(i, th, self.cfg.cutoff, self.cfg.chi_max,
-                                                 move_right=left_to_right)
+                force = self._frozen_ranks.pop(0) if self._frozen_ranks is not None else None
+                eps, flagged, kept = self.mps.split(i, th, self.cfg.cutoff, self.cfg.chi_max,
+                                                    move_right=left_to_right, force_k=force)
+                self.rank_log.append(kept)
                 self.f_est *= (1.0 - eps)
                 self.flags += int(flagged)
             changed_total += changed
@@ -228,12 +244,17 @@ def apply_dense_two_site(v: np.ndarray, d: int, n: int, site: int, u: np.ndarray
     return np.einsum("xy,ayb->axb", u, t).reshape(-1)
 
 
-def run_circuit(circuit, candidates, cfg: Config, record_states: bool = False) -> Gcamps:
-    """Run a workload circuit (bricks then phase gates, layer by layer)."""
-    g = Gcamps(circuit.d, circuit.n, cfg, candidates)
+def run_circuit(circuit, candidates, cfg: Config, record_states: bool = False,
+                phases_override=None, frozen=None) -> Gcamps:
+    """Run a workload circuit (bricks then phase gates, layer by layer).
+    ``phases_override[param]`` replaces the angles of parametrised gates."""
+    g = Gcamps(circuit.d, circuit.n, cfg, candidates, frozen=frozen)
     for layer in circuit.layers:
         for b in layer.bricks:
             g.apply_clifford(b.site, b.word.gens, b.word.weyl)
         for ph in layer.phases:
-            g.apply_phase_rotation(ph.site, ph.phi)
+            phi = ph.phi
+            if phases_override is not None and ph.param >= 0:
+                phi = phases_override[ph.param]
+            g.apply_phase_rotation(ph.site, phi)
     return g

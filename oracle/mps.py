@@ -124,14 +124,19 @@ class MPS:
         return np.einsum("asm,mtb->astb", self.tensors[i], self.tensors[i + 1])
 
     def split(self, i: int, theta: np.ndarray, cutoff: float, chi_max: int,
-              move_right: bool) -> Tuple[float, bool, int]:
+              move_right: bool, force_k: int | None = None) -> Tuple[float, bool, int]:
         """SVD-split theta back into sites (i, i+1) with R-TRUNC.
 
         Returns (eps, flagged, kept).  The centre ends on i+1 (move_right) or i.
+        ``force_k`` replaces the rule's rank (frozen-decision replay); eps is then the
+        discarded weight of that rank.
         """
         cl, d, _, cr = theta.shape
         u, s, vh = np.linalg.svd(theta.reshape(cl * d, d * cr), full_matrices=False)
         k, eps, flagged = rtrunc(s, cutoff, chi_max)
+        if force_k is not None:
+            k, flagged = int(force_k), False
+            eps = float(np.sum(s[k:] ** 2) / np.sum(s ** 2))
         sk = s[:k] / np.linalg.norm(s[:k])
         u, vh = u[:, :k], vh[:k, :]
         if move_right:
@@ -144,20 +149,26 @@ class MPS:
             self.centre = i
         return eps, flagged, k
 
-    def truncate_sweep_left(self, l: int, r: int, cutoff: float, chi_max: int
+    def truncate_sweep_left(self, l: int, r: int, cutoff: float, chi_max: int,
+                            force_ks: List[int] | None = None
                             ) -> Tuple[List[float], List[bool]]:
         """Compression after an operator on [l, r]: QR left-to-right over [l, r-1], then
-        SVD right-to-left for i = r..l+1 with R-TRUNC; the centre ends on l."""
+        SVD right-to-left for i = r..l+1 with R-TRUNC; the centre ends on l.
+        ``force_ks`` (one rank per split, in order) replaces the rule's ranks."""
         self.move_centre(l)
         for i in range(l, r):
             self._shift_right(i)
         self.centre = r
         epss, flags = [], []
-        for i in range(r, l, -1):
+        self.last_ks = []
+        for t, i in enumerate(range(r, l, -1)):
             a = self.tensors[i]
             cl, d, cr = a.shape
             u, s, vh = np.linalg.svd(a.reshape(cl, d * cr), full_matrices=False)
             k, eps, flagged = rtrunc(s, cutoff, chi_max)
+            if force_ks is not None:
+                k, flagged = int(force_ks[t]), False
+                eps = float(np.sum(s[k:] ** 2) / np.sum(s ** 2))
             sk = s[:k] / np.linalg.norm(s[:k])
             self.tensors[i] = vh[:k].reshape(k, d, cr)
             self.tensors[i - 1] = np.einsum("asb,bc->asc", self.tensors[i - 1],
@@ -165,6 +176,7 @@ class MPS:
             self.centre = i - 1
             epss.append(eps)
             flags.append(flagged)
+            self.last_ks.append(k)
         return epss, flags
 
     # ----------------------------------------------------------- operators
