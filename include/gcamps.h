@@ -248,6 +248,56 @@ int32_t gcamps_batch_workspace_bytes(const gcamps_batch_item* items, int32_t cou
 int32_t gcamps_batch_run(const gcamps_batch_item* items, int32_t count, const gcamps_candset* set,
                          int32_t lanes, void* dev_workspace, size_t bytes, double stats[16]);
 
+/* ---------------------------------------------------------------------------
+ * Gradient of an observable loss with respect to phase-gate angles.
+ *
+ * Loss: L(theta) = Re sum_j <psi|Z_j|psi> over all sites j (the observables of
+ * §3: each Z_j is commuted through the final Clifford into a Weyl string and
+ * evaluated on the MPS by transfer matrices).  A phase op whose op_param entry
+ * is b >= 0 is diag(e^{i phi}) with phi = (0, theta[(d-1)b], ...,
+ * theta[(d-1)b + d-2]); op_param -1 (or op_param NULL) keeps the op's own phi.
+ * The derivative is taken with the method's discrete decisions (disentangler
+ * choices and the kept rank of every factorisation) frozen at the recording
+ * point theta0, which makes the truncated forward pass a smooth function of
+ * theta.  It is computed in reverse mode: replay with checkpoints before every
+ * gate, then gate by gate a taped replay and its reverse sweep through the MPO
+ * site maps, the disentangler unitaries and the truncated factorisations.
+ *
+ * Workspace: one device buffer; its first gcamps_workspace_bytes(cfg) bytes
+ * (rounded up to 256) hold the state, the rest is the arena for checkpoints,
+ * the tape of one gate and the adjoint tensors.  ECAPACITY when the arena is
+ * too small.  The gcamps_grad object owns its state and stream use; it must not
+ * outlive the workspace.
+ * ------------------------------------------------------------------------- */
+typedef struct gcamps_grad gcamps_grad;
+
+/* Run the circuit `ops` at theta0 (= theta) with the ordinary forward pass and
+ * record the decisions; *loss (may be NULL) receives L(theta0).
+ * op_param: n_ops ints (entries of Clifford ops are ignored) or NULL;
+ * n_theta: multiple of d - 1 covering every parameter block used.
+ * Errors: EINVAL, EUNSUPPORTED, EWORKSPACE, ECAPACITY, ENUMERIC, EDEVICE. */
+int32_t gcamps_grad_record(const gcamps_config* cfg, const gcamps_op* ops, int64_t n_ops,
+                           const int32_t* op_param, const double* theta, int32_t n_theta,
+                           const gcamps_candset* set, void* dev_workspace, size_t bytes,
+                           void* hip_stream, gcamps_grad** out, double* loss);
+
+/* L(theta) of the frozen replay (equals the recorded loss at theta0, bit for bit).
+ * Errors: EINVAL, ECAPACITY, ENUMERIC, EDEVICE. */
+int32_t gcamps_grad_loss(gcamps_grad* g, const double* theta, double* loss);
+
+/* dL/dtheta (n_theta host doubles) of the frozen replay at theta, and L(theta)
+ * into *loss (may be NULL).  Errors: EINVAL, ECAPACITY, ENUMERIC, EDEVICE. */
+int32_t gcamps_grad_gradient(gcamps_grad* g, const double* theta, double* loss, double* grad);
+
+/* Statistics (8 doubles): [0] checkpointed replay and loss adjoint of the last
+ * gradient in ms, [1] its reverse sweep in ms, [2] peak arena bytes, [3] taped steps,
+ * [4] non-Clifford gates, [5] recording pass in ms, [6] recorded factorisations,
+ * [7] recorded disentangler choices. */
+int32_t gcamps_grad_stats(gcamps_grad* g, double out[8]);
+
+/* Release the gradient object; NULL is a no-op. */
+int32_t gcamps_grad_destroy(gcamps_grad* g);
+
 /* Thread-local message for the last failed call on this thread. */
 const char* gcamps_last_error(void);
 

@@ -15,7 +15,7 @@ then a smooth function of theta and its derivative is well defined.  Three defin
   differentiating one phase gate at a time, d/dphi_j diag(e^{i phi}) = i |j><j| diag(e^{i phi}).
   Equals the GCAMPS derivative whenever nothing is truncated.
 * ``fd_gradient``: central differences of the frozen GCAMPS replay (error O(h^2) plus
-  rounding / h).
+  rounding / h), optionally Richardson-extrapolated (O(h^4)).
 * ``replay_loss``: the frozen GCAMPS forward pass itself.
 """
 from __future__ import annotations
@@ -106,15 +106,23 @@ def replay_loss(circuit, candidates, cfg: Config, theta, frozen) -> float:
 
 
 def fd_gradient(circuit, candidates, cfg: Config, theta, frozen, h: float = 1e-6,
-                params: Sequence[int] | None = None) -> np.ndarray:
-    """Central differences (L(theta + h e_k) - L(theta - h e_k)) / 2h of the frozen replay."""
+                params: Sequence[int] | None = None, richardson: bool = False) -> np.ndarray:
+    """Central differences D(h) = (L(theta + h e_k) - L(theta - h e_k)) / 2h of the frozen
+    replay (error O(h^2)); with ``richardson`` the extrapolation (4 D(h) - D(2h)) / 3, whose
+    error is O(h^4)."""
     theta = np.asarray(theta, dtype=np.float64)
     idx = range(len(theta)) if params is None else params
     g = np.full(len(theta), np.nan)
-    for k in idx:
+
+    def central(k, step):
         tp, tm = theta.copy(), theta.copy()
-        tp[k] += h
-        tm[k] -= h
-        g[k] = (replay_loss(circuit, candidates, cfg, tp, frozen)
-                - replay_loss(circuit, candidates, cfg, tm, frozen)) / (2.0 * h)
+        tp[k] += step
+        tm[k] -= step
+        return (replay_loss(circuit, candidates, cfg, tp, frozen)
+                - replay_loss(circuit, candidates, cfg, tm, frozen)) / (2.0 * step)
+
+    for k in idx:
+        g[k] = central(k, h)
+        if richardson:
+            g[k] = (4.0 * g[k] - central(k, 2.0 * h)) / 3.0
     return g

@@ -13,7 +13,7 @@
 #include <memory>
 #include <mutex>
 
-#include "kernels.h"
+#include "ctx.h"
 
 using namespace gc;
 
@@ -35,14 +35,56 @@ bool is_prime(int d) {
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-struct Layout {
-  size_t slot_elems, theta_elems, mcap, m_pad, ncand, ntp;
-  int nslots;
-  size_t off_slots, off_theta, off_G, off_U, off_Z, off_Utmp, off_B, off_B2, off_sig2, off_sig, off_lam,
-      off_perm, off_eigG, off_eigV, off_flags, off_s2, off_s2w, off_wlist, off_partial, off_nbuf, nbuf_bytes, off_q64, off_q32,
-      off_qinv, off_tab, off_target, off_weyl, off_err, off_status, off_luts, off_sites, total;
-};
 
+void validate_config(const gcamps_config* c) {
+  GC_CHECK(c != nullptr, GCAMPS_EINVAL, "config is null");
+  GC_CHECK(c->d >= 2 && c->d <= kMaxD, GCAMPS_EINVAL, "d out of range [2, 7]");
+  GC_CHECK(is_prime(c->d), GCAMPS_EUNSUPPORTED, "d must be prime (decomposition over the field Z_d)");
+  GC_CHECK(c->n >= 2 && c->n <= kMaxN, GCAMPS_EINVAL, "n out of range [2, 128]");
+  GC_CHECK(c->chi_max >= 1 && (size_t)c->chi_max * c->d <= 4096, GCAMPS_EINVAL, "chi_max out of range");
+  GC_CHECK(c->cutoff >= 0.0 && c->cutoff < 1.0, GCAMPS_EINVAL, "cutoff out of range [0, 1)");
+  GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->score_prec == GCAMPS_SCORE_FP32, GCAMPS_EINVAL,
+           "score_prec must be GCAMPS_SCORE_FP64 or GCAMPS_SCORE_FP32");
+  GC_CHECK(c->tie_tol >= 0.0, GCAMPS_EINVAL, "tie_tol must be >= 0");
+  GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->near_tie >= 1e-6, GCAMPS_EINVAL, "near_tie must be >= 1e-6");
+  GC_CHECK(c->max_sweeps >= 0, GCAMPS_EINVAL, "max_sweeps must be >= 0");
+  GC_CHECK(c->max_candidates >= 1 && c->max_candidates <= 65536, GCAMPS_EINVAL, "max_candidates out of range");
+}
+
+template <typename F>
+int32_t guarded(gcamps_ctx* ctx, F&& f);
+
+}  // namespace
+
+
+namespace {
+
+template <typename F>
+int32_t guarded(gcamps_ctx* ctx, F&& f) {
+  try {
+    if (ctx && ctx->poisoned) throw Error{GCAMPS_EDEVICE, "context poisoned by an earlier device/numeric error"};
+    auto t0 = std::chrono::steady_clock::now();
+    f();
+    if (ctx)
+      ctx->stats[7] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return GCAMPS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    if (ctx && (e.code == GCAMPS_EDEVICE || e.code == GCAMPS_ENUMERIC)) ctx->poisoned = true;
+    return e.code;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return GCAMPS_EINVAL;
+  }
+}
+
+}  // namespace
+
+namespace gc {
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace gc
+
+namespace gc {
 Layout make_layout(const gcamps_config& c) {
   Layout L{};
   const size_t d = c.d, chi = c.chi_max;
@@ -97,358 +139,6 @@ Layout make_layout(const gcamps_config& c) {
   L.total = o;
   return L;
 }
-
-void validate_config(const gcamps_config* c) {
-  GC_CHECK(c != nullptr, GCAMPS_EINVAL, "config is null");
-  GC_CHECK(c->d >= 2 && c->d <= kMaxD, GCAMPS_EINVAL, "d out of range [2, 7]");
-  GC_CHECK(is_prime(c->d), GCAMPS_EUNSUPPORTED, "d must be prime (decomposition over the field Z_d)");
-  GC_CHECK(c->n >= 2 && c->n <= kMaxN, GCAMPS_EINVAL, "n out of range [2, 128]");
-  GC_CHECK(c->chi_max >= 1 && (size_t)c->chi_max * c->d <= 4096, GCAMPS_EINVAL, "chi_max out of range");
-  GC_CHECK(c->cutoff >= 0.0 && c->cutoff < 1.0, GCAMPS_EINVAL, "cutoff out of range [0, 1)");
-  GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->score_prec == GCAMPS_SCORE_FP32, GCAMPS_EINVAL,
-           "score_prec must be GCAMPS_SCORE_FP64 or GCAMPS_SCORE_FP32");
-  GC_CHECK(c->tie_tol >= 0.0, GCAMPS_EINVAL, "tie_tol must be >= 0");
-  GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->near_tie >= 1e-6, GCAMPS_EINVAL, "near_tie must be >= 1e-6");
-  GC_CHECK(c->max_sweeps >= 0, GCAMPS_EINVAL, "max_sweeps must be >= 0");
-  GC_CHECK(c->max_candidates >= 1 && c->max_candidates <= 65536, GCAMPS_EINVAL, "max_candidates out of range");
-}
-
-template <typename F>
-int32_t guarded(gcamps_ctx* ctx, F&& f);
-
-}  // namespace
-
-// ------------------------------------------------------------------------------- ctx
-struct gcamps_ctx {
-  gcamps_config cfg{};
-  Layout lay{};
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;
-  int d = 0, n = 0;
-  bool poisoned = false;
-  // device regions
-  int *tx = nullptr, *tz = nullptr, *tp = nullptr, *target = nullptr, *derr = nullptr, *dsites = nullptr;
-  uint32_t* dluts = nullptr;
-  DevWeyl* weyl = nullptr;
-  DevStatus* st = nullptr;
-  z64 *theta = nullptr, *G = nullptr, *U = nullptr, *Z = nullptr, *Utmp = nullptr, *B = nullptr, *B2 = nullptr;
-  double *sig2 = nullptr, *sig = nullptr, *lam = nullptr, *s2 = nullptr, *s2w = nullptr, *partial = nullptr;
-  void* nbuf = nullptr;
-  int *perm = nullptr, *wlist = nullptr;
-  z64* q64 = nullptr;
-  c32* q32 = nullptr;
-  uint32_t* qinv = nullptr;
-  EigWork eig{};
-  // MPS
-  std::vector<z64*> site;
-  z64* Lbuf = nullptr;
-  z64* Rbuf = nullptr;
-  z64* spare = nullptr;
-  std::vector<int> chi;  // chi[0..n], bond j between sites j-1 and j
-  int centre = 0;
-  // candidates
-  int ncand = 0;
-  uint64_t cand_uid = 0;
-  // pinned staging
-  char* pinned = nullptr;
-  size_t pinned_bytes = 0;
-  hipEvent_t stage_ev = nullptr;
-  bool stage_pending = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
-  std::vector<hipEvent_t> gram_ev;  // event pairs around the Gram-purity launches of one bond
-  // host state
-  double f_est = 1.0;
-  std::vector<int32_t> choice_log;
-  int64_t gates = 0;
-  double stats[16] = {0};
-
-  ~gcamps_ctx() {
-    if (pinned) (void)hipHostFree(pinned);
-    if (stage_ev) (void)hipEventDestroy(stage_ev);
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
-    if (ev2) (void)hipEventDestroy(ev2);
-    if (ev3) (void)hipEventDestroy(ev3);
-    for (auto e : gram_ev) (void)hipEventDestroy(e);
-  }
-
-  // ---------------------------------------------------------------- staging
-  char* stage_begin() {
-    if (stage_pending) {
-      GC_HIP(hipEventSynchronize(stage_ev));
-      stage_pending = false;
-    }
-    return pinned;
-  }
-  void stage_upload(void* dst, size_t bytes) {
-    GC_HIP(hipMemcpyAsync(dst, pinned, bytes, hipMemcpyHostToDevice, stream));
-    GC_HIP(hipEventRecord(stage_ev, stream));
-    stage_pending = true;
-  }
-  void read_status(DevStatus& h) {
-    GC_HIP(hipMemcpyAsync(&h, st, sizeof(DevStatus), hipMemcpyDeviceToHost, stream));
-    GC_HIP(hipStreamSynchronize(stream));
-  }
-
-  int dim_l(int i) const { return chi[i]; }
-  int dim_r(int i) const { return chi[i + 1]; }
-
-  // ---------------------------------------------------------------- factorisation
-  // Split M (p x q, row-major) into L (p x k) R (k x q).  mode 0: truncation rule with
-  // renormalisation; mode 1: exact (rank floor only).  left_ortho: L has orthonormal columns
-  // (else R has orthonormal rows).  Returns the status block of the final pass.
-  DevStatus factorize(const z64* M, int p, int q, int mode, int left_ortho, z64* Lout, z64* Rout) {
-    const bool wide = p <= q;
-    const int m = wide ? p : q, kW = wide ? q : p;
-    GC_CHECK((size_t)m <= lay.mcap && (size_t)m * kW <= lay.slot_elems, GCAMPS_ECAPACITY,
-             "factorisation exceeds workspace capacity");
-    const z64 one = {1.0, 0.0};
-    if (wide)
-      launch_zgemm(stream, 0, 1, m, m, q, M, q, M, q, G, m, one, 0, 1);
-    else
-      launch_zgemm(stream, 1, 0, m, m, p, M, q, M, q, G, m, one, 0, 1);
-    eig_hermitian(stream, G, m, m, U, m, lam, 0, eig, st, nullptr);
-    if (wide)
-      launch_zgemm(stream, 1, 0, m, q, m, U, m, M, q, B, q, one, 0, 0);
-    else
-      launch_zgemm(stream, 1, 1, m, p, m, U, m, M, q, B, p, one, 0, 0);
-    launch_rownorm2(stream, B, m, kW, kW, sig2);
-    launch_trunc(stream, sig2, m, cfg.cutoff, cfg.chi_max, mode, perm, sig, st);
-    DevStatus h;
-    read_status(h);
-    GC_CHECK(m > kSmallEig || h.converged, GCAMPS_ENUMERIC, "eigensolver did not converge");
-    stats[5] += 8.0 * (double)m * m * kW * 2.0;
-    if (h.need_pass2) {
-      // accurate second pass on the nearly diagonal Gram of B (relative criterion)
-      launch_zgemm(stream, 0, 1, m, m, kW, B, kW, B, kW, G, m, one, 0, 1);
-      eig_hermitian(stream, G, m, m, Z, m, lam, 1, eig, st, nullptr);
-      launch_zgemm(stream, 0, 0, m, m, m, U, m, Z, m, Utmp, m, one, 0, 0);
-      std::swap(U, Utmp);
-      launch_zgemm(stream, 1, 0, m, kW, m, Z, m, B, kW, B2, kW, one, 0, 0);
-      std::swap(B, B2);
-      launch_rownorm2(stream, B, m, kW, kW, sig2);
-      launch_trunc(stream, sig2, m, cfg.cutoff, cfg.chi_max, mode, perm, sig, st);
-      read_status(h);
-      GC_CHECK(m > kSmallEig || h.converged, GCAMPS_ENUMERIC, "eigensolver did not converge (second pass)");
-      stats[5] += 8.0 * (double)m * m * kW * 2.0;
-    }
-    GC_CHECK(std::isfinite(h.eps) && h.kept >= 1, GCAMPS_ENUMERIC, "factorisation produced non-finite values");
-    launch_emit(stream, wide ? 1 : 0, left_ortho, mode == 0 ? 1 : 0, p, q, h.kept, U, m, B, kW, perm, sig, Lout,
-                Rout);
-    return h;
-  }
-
-  // ---------------------------------------------------------------- centre moves (exact)
-  void move_right(int i) {  // centre i -> i+1
-    const int p = chi[i] * d, q = chi[i + 1];
-    DevStatus h = factorize(site[i], p, q, 1, 1, Lbuf, Rbuf);
-    const int k = h.kept;
-    std::swap(site[i], Lbuf);
-    const int ncols = d * chi[i + 2];
-    launch_zgemm(stream, 0, 0, k, ncols, q, Rbuf, q, site[i + 1], ncols, spare, ncols, z64{1.0, 0.0}, 0, 0);
-    std::swap(site[i + 1], spare);
-    chi[i + 1] = k;
-    centre = i + 1;
-  }
-  void move_left(int i) {  // centre i -> i-1
-    const int p = chi[i], q = d * chi[i + 1];
-    DevStatus h = factorize(site[i], p, q, 1, 0, Lbuf, Rbuf);
-    const int k = h.kept;
-    std::swap(site[i], Rbuf);
-    const int nrows = chi[i - 1] * d;
-    launch_zgemm(stream, 0, 0, nrows, k, p, site[i - 1], p, Lbuf, k, spare, k, z64{1.0, 0.0}, 0, 0);
-    std::swap(site[i - 1], spare);
-    chi[i] = k;
-    centre = i - 1;
-  }
-  void move_centre(int target) {
-    while (centre < target) move_right(centre);
-    while (centre > target) move_left(centre);
-  }
-
-  // ---------------------------------------------------------------- bottom loop
-  void phase_rotation(int s, const double* phi) {
-    // target Z_s
-    int* tg = reinterpret_cast<int*>(stage_begin());
-    for (int i = 0; i < 2 * n + 1; ++i) tg[i] = 0;
-    tg[n + s] = 1;
-    stage_upload(target, (2 * n + 1) * sizeof(int));
-    launch_weyl_extract(stream, n, d, tx, tz, tp, target, weyl, derr);
-    DevWeyl P;
-    int err = 0;
-    GC_HIP(hipMemcpyAsync(&P, weyl, sizeof(DevWeyl), hipMemcpyDeviceToHost, stream));
-    GC_HIP(hipMemcpyAsync(&err, derr, sizeof(int), hipMemcpyDeviceToHost, stream));
-    GC_HIP(hipStreamSynchronize(stream));
-    GC_CHECK(err == 0 && P.l >= 0, GCAMPS_ENUMERIC, "tableau decomposition failed");
-    const int l = P.l, r = P.r;
-    // U = diag(e^{i phi_j}) = sum_b c_b Z^b with c_b = (1/d) sum_j e^{i phi_j} omega^{-bj}
-    MpoCoeff co;
-    int sd = 0;
-    for (int i = 0; i < n; ++i) sd += P.x[i] * P.z[i];
-    for (int b = 0; b < d; ++b) {
-      std::complex<double> cb = 0.0;
-      for (int j = 0; j < d; ++j) cb += std::polar(1.0, phi[j] - 2.0 * M_PI * b * j / d);
-      cb /= (double)d;
-      // phase of P^b = tau^{b p + 2 <delta, s> b(b-1)/2}
-      int ph = (b * P.p + 2 * (sd % d) * (b * (b - 1) / 2)) % (2 * d);
-      std::complex<double> kb = cb * std::polar(1.0, M_PI * ph / d);
-      co.k[b] = z64{kb.real(), kb.imag()};
-      co.w[b] = z64{std::cos(2.0 * M_PI * b / d), std::sin(2.0 * M_PI * b / d)};
-    }
-    move_centre(l);
-    for (int i = l; i <= r; ++i) {
-      int kind = (l == r) ? 3 : (i == l ? 0 : (i == r ? 2 : 1));
-      launch_mpo_site(stream, kind, d, chi[i], chi[i + 1], P.x[i], P.z[i], co, site[i], spare);
-      std::swap(site[i], spare);
-    }
-    for (int j = l + 1; j <= r; ++j) chi[j] *= d;
-    if (r > l) {
-      for (int i = l; i < r; ++i) move_right(i);
-      for (int i = r; i > l; --i) {
-        const int p = chi[i], q = d * chi[i + 1];
-        DevStatus h = factorize(site[i], p, q, 0, 0, Lbuf, Rbuf);
-        const int k = h.kept;
-        std::swap(site[i], Rbuf);
-        const int nrows = chi[i - 1] * d;
-        launch_zgemm(stream, 0, 0, nrows, k, p, site[i - 1], p, Lbuf, k, spare, k, z64{1.0, 0.0}, 0, 0);
-        std::swap(site[i - 1], spare);
-        chi[i] = k;
-        centre = i - 1;
-        f_est *= (1.0 - h.eps);
-        stats[3] += h.flagged;
-      }
-    }
-    gates += 1;
-    stats[0] += 1;
-  }
-
-  void disentangle(int* out_sweeps, int* out_changed) {
-    GC_CHECK(ncand >= 1, GCAMPS_EINVAL, "no candidate set attached");
-    int sweeps = 0, changed_total = 0;
-    const int prec = cfg.score_prec;
-    for (int sw = 0; sw < cfg.max_sweeps; ++sw) {
-      ++sweeps;
-      const bool ltr = (sw % 2 == 0);
-      int changed = 0;
-      for (int t = 0; t < n - 1; ++t) {
-        const int i = ltr ? t : n - 2 - t;
-        move_centre(ltr ? i : i + 1);
-        const int cl = chi[i], cm = chi[i + 1], cr = chi[i + 2];
-        launch_zgemm(stream, 0, 0, cl * d, d * cr, cm, site[i], cm, site[i + 1], d * cr, theta, d * cr,
-                     z64{1.0, 0.0}, 0, 0);
-        const int mm = std::min(cl * d, d * cr), kk = std::max(cl * d, d * cr);
-        const size_t pcap = lay.ncand * lay.ntp * 2;
-        const double pflops = 4.0 * mm * mm * kk + 8.0 * std::pow((double)d, 4) * cl * cr;
-        GC_HIP(hipEventRecord(ev0, stream));
-        int gram_used = 0;
-        launch_score(stream, prec, d, cl, cr, theta, q64, q32, nullptr, ncand, nullptr, s2, partial, pcap, nbuf,
-                     lay.nbuf_bytes, gram_ev.data(), (int)gram_ev.size(), &gram_used);
-        GC_HIP(hipEventRecord(ev1, stream));
-        if (prec == GCAMPS_SCORE_FP64) {
-          launch_select(stream, ncand, s2, cfg.tie_tol, st);
-        } else {
-          launch_window(stream, ncand, s2, cfg.near_tie, wlist, st);
-          GC_HIP(hipEventRecord(ev2, stream));
-          launch_score(stream, GCAMPS_SCORE_FP64, d, cl, cr, theta, q64, q32, wlist, ncand, &st->nwindow, s2w,
-                       partial, pcap, nbuf, lay.nbuf_bytes);
-          GC_HIP(hipEventRecord(ev3, stream));
-          launch_select_window(stream, wlist, s2w, cfg.tie_tol, st);
-        }
-        stats[4] += (double)ncand * pflops;
-        stats[10] += 1;
-        launch_apply_q(stream, d, cl, cr, st, q64, theta);
-        launch_tableau_right_mult(stream, n, d, i, st, qinv, tx, tz, tp);
-        // When the identity is kept, Theta = A_i A_{i+1} with the neighbour of the centre
-        // orthonormal (right-orthonormal A_{i+1} when sweeping left to right, left-orthonormal
-        // A_i otherwise), so Theta's Schmidt values are those of the centre tensor alone and the
-        // split only needs the factorisation of that (smaller) tensor.
-        bool shortcut = false;
-        if (mm > kSmallEig) {
-          DevStatus pre;
-          read_status(pre);
-          shortcut = (pre.cstar == 0);
-        }
-        DevStatus h;
-        if (shortcut && ltr) {
-          h = factorize(site[i], cl * d, cm, 0, 1, Lbuf, Rbuf);
-          const int k = h.kept;
-          launch_zgemm(stream, 0, 0, k, d * cr, cm, Rbuf, cm, site[i + 1], d * cr, spare, d * cr, z64{1.0, 0.0}, 0, 0);
-          std::swap(site[i], Lbuf);
-          std::swap(site[i + 1], spare);
-        } else if (shortcut) {
-          h = factorize(site[i + 1], cm, d * cr, 0, 0, Lbuf, Rbuf);
-          const int k = h.kept;
-          launch_zgemm(stream, 0, 0, cl * d, k, cm, site[i], cm, Lbuf, k, spare, k, z64{1.0, 0.0}, 0, 0);
-          std::swap(site[i + 1], Rbuf);
-          std::swap(site[i], spare);
-        } else {
-          h = factorize(theta, cl * d, d * cr, 0, ltr ? 1 : 0, Lbuf, Rbuf);
-          std::swap(site[i], Lbuf);
-          std::swap(site[i + 1], Rbuf);
-        }
-        stats[14] += shortcut ? 1 : 0;
-        float ms = 0.f;
-        GC_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-        stats[6] += ms;
-        if (gram_used > 0) {  // Gram-purity kernel alone: algorithmic 4 m^2 k flop per candidate
-          for (int e = 0; e < gram_used; ++e) {
-            float gm = 0.f;
-            GC_HIP(hipEventElapsedTime(&gm, gram_ev[2 * e], gram_ev[2 * e + 1]));
-            stats[12] += gm;
-          }
-          stats[11] += gram_used;
-          stats[13] += (double)ncand * 4.0 * mm * mm * kk;
-        }
-        stats[1] += 1;
-        if (prec != GCAMPS_SCORE_FP64) {
-          stats[2] += h.nwindow;
-          stats[8] += (double)h.nwindow * pflops;
-          GC_HIP(hipEventElapsedTime(&ms, ev2, ev3));
-          stats[9] += ms;
-        }
-        chi[i + 1] = h.kept;
-        centre = ltr ? i + 1 : i;
-        f_est *= (1.0 - h.eps);
-        stats[3] += h.flagged;
-        choice_log.push_back((int32_t)(gates - 1));
-        choice_log.push_back(sw);
-        choice_log.push_back(i);
-        choice_log.push_back(h.cstar);
-        if (h.cstar != 0) ++changed;
-      }
-      changed_total += changed;
-      if (changed == 0) break;
-    }
-    if (out_sweeps) *out_sweeps = sweeps;
-    if (out_changed) *out_changed = changed_total;
-  }
-};
-
-namespace {
-
-template <typename F>
-int32_t guarded(gcamps_ctx* ctx, F&& f) {
-  try {
-    if (ctx && ctx->poisoned) throw Error{GCAMPS_EDEVICE, "context poisoned by an earlier device/numeric error"};
-    auto t0 = std::chrono::steady_clock::now();
-    f();
-    if (ctx)
-      ctx->stats[7] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    return GCAMPS_OK;
-  } catch (const Error& e) {
-    g_last_error = e.msg;
-    if (ctx && (e.code == GCAMPS_EDEVICE || e.code == GCAMPS_ENUMERIC)) ctx->poisoned = true;
-    return e.code;
-  } catch (const std::exception& e) {
-    g_last_error = e.what();
-    return GCAMPS_EINVAL;
-  }
-}
-
-}  // namespace
-
-namespace gc {
-void set_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace gc
 
 // ------------------------------------------------------------------------------- C ABI

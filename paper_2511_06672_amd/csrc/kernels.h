@@ -35,9 +35,10 @@ struct EigWork {
 void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu, double* lam,
                    int rel, EigWork& w, DevStatus* st, int* host_sweeps);
 void launch_rownorm2(hipStream_t s, const z64* B, int m, int k, int ldb, double* out);
-// Sort, truncation rule, pass-2 decision.  mode 0 = truncate (cutoff, chi_max), 1 = floor only.
+// Sort, truncation rule, pass-2 decision.  mode 0 = truncate (cutoff, chi_max), 1 = floor only;
+// force_k > 0 keeps exactly that rank (frozen-decision replay).
 void launch_trunc(hipStream_t s, const double* sig2, int m, double cutoff, int chi_max, int mode,
-                  int* perm, double* sig_sorted, DevStatus* st);
+                  int force_k, int* perm, double* sig_sorted, DevStatus* st);
 // Write the two factors (see kernels_linalg.hip for the case table).
 void launch_emit(hipStream_t s, int wide, int left_ortho, int renorm, int p, int q, int kept,
                  const z64* U, int ldu, const z64* B, int ldb, const int* perm, const double* sig,
@@ -86,4 +87,29 @@ void launch_clifford_dense(hipStream_t s, int n, int d, long long D, const int* 
                            z64* out);
 void launch_scale(hipStream_t s, z64* v, size_t count, z64 f);
 void launch_norm2(hipStream_t s, const z64* v, size_t count, double* out);
+
+// ------------------------------------------------------------------ reverse sweep (kernels_adjoint.hip)
+// out[0] = 1/sqrt(sum_{j<k} sig_j^2) when renorm, else 1.
+void launch_kept_norm(hipStream_t s, const double* sig, int k, int renorm, double* out);
+// X (rows x cols) scaled by 1/(sig_c^2 rn^2) per column (by_cols) or per row.
+void launch_inv_gram_scale(hipStream_t s, z64* X, int rows, int cols, int by_cols, const double* sig,
+                           const double* rn);
+// out[0] = Re sum conj(a) b.
+void launch_dot_re(hipStream_t s, const z64* a, const z64* b, size_t count, double* out);
+// Xbar = rn (Nbar - N dot).
+void launch_renorm_bwd(hipStream_t s, const z64* Nbar, const z64* N, size_t count, const double* rn,
+                       const double* dot, z64* Xbar);
+// dst[a] = src[perm[a]] for rows a < keep_rows, zero rows below (m x cols).
+void launch_gather_rows(hipStream_t s, const z64* src, const int* perm, int m, int cols, int keep_rows, z64* dst);
+// dst[:, a] = src[:, perm[a]] (m x m).
+void launch_gather_cols(hipStream_t s, const z64* src, const int* perm, int m, z64* dst);
+// Kept/discarded mixing matrix of the truncated-split adjoint (sorted basis, k kept).
+void launch_trunc_mix(hipStream_t s, const z64* G1, int m, int k, const double* sig, z64* Zc);
+// Transpose of the MPO site map and the gradient of its coefficients (kinds 0 and 3).
+void launch_mpo_site_bwd(hipStream_t s, int kind, int d, int chil, int chir, int dx, int dz, const MpoCoeff& co,
+                         const z64* obar, z64* ibar);
+void launch_mpo_coeff_bwd(hipStream_t s, int kind, int d, int chil, int chir, int dx, int dz, const MpoCoeff& co,
+                          const z64* in, const z64* obar, z64* kbar);
+// theta <- Q_c^dagger theta.
+void launch_apply_qh(hipStream_t s, int d, int chil, int chir, int c, const z64* qmats, z64* theta);
 }  // namespace gc

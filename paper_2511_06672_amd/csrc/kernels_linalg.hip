@@ -586,10 +586,11 @@ __global__ void k_rownorm2(const z64* __restrict__ B, int m, int k, int ldb, dou
 //   k_cut = smallest k >= 1 with tail[k] <= cutoff; k_floor = #{sigma_j > 1e-13 sigma_0}
 //   k = min(k_cut, k_floor, chi_max); degeneracy guard as in the truncation rule.
 // mode 1 keeps k_floor (exact moves).  need_pass2 when a kept value is below 1e-12 sig2_0.
+// force_k > 0 replaces the rule by that rank (frozen-decision replay; never flagged).
 constexpr int TRUNC_MAX = 4096;
 __global__ __launch_bounds__(1024) void k_trunc(const double* __restrict__ sig2, int m, double cutoff, int chi_max,
-                                                int mode, int* __restrict__ perm, double* __restrict__ sig_sorted,
-                                                DevStatus* st) {
+                                                int mode, int force_k, int* __restrict__ perm,
+                                                double* __restrict__ sig_sorted, DevStatus* st) {
   __shared__ double key[TRUNC_MAX];
   __shared__ int idx[TRUNC_MAX];
   int P2 = 1;
@@ -661,6 +662,10 @@ __global__ __launch_bounds__(1024) void k_trunc(const double* __restrict__ sig2,
             k = j;
         }
       }
+    }
+    if (force_k > 0) {
+      k = force_k < m ? force_k : m;
+      flagged = 0;
     }
     double eps = 0.0;
     for (int i = m - 1; i >= k; --i) eps += key[i] / total;
@@ -827,10 +832,11 @@ void launch_rownorm2(hipStream_t s, const z64* B, int m, int k, int ldb, double*
   GC_LAUNCH_CHECK();
 }
 
-void launch_trunc(hipStream_t s, const double* sig2, int m, double cutoff, int chi_max, int mode, int* perm,
-                  double* sig_sorted, DevStatus* st) {
+void launch_trunc(hipStream_t s, const double* sig2, int m, double cutoff, int chi_max, int mode, int force_k,
+                  int* perm, double* sig_sorted, DevStatus* st) {
   GC_CHECK(m <= TRUNC_MAX, GCAMPS_ECAPACITY, "truncation: matrix side exceeds 4096");
-  hipLaunchKernelGGL(k_trunc, dim3(1), dim3(1024), 0, s, sig2, m, cutoff, chi_max, mode, perm, sig_sorted, st);
+  hipLaunchKernelGGL(k_trunc, dim3(1), dim3(1024), 0, s, sig2, m, cutoff, chi_max, mode, force_k, perm, sig_sorted,
+                     st);
   GC_LAUNCH_CHECK();
 }
 

@@ -27,7 +27,8 @@ SYMBOLS = [
     "gcamps_candset_destroy", "gcamps_set_candset", "gcamps_disentangle", "gcamps_expectation",
     "gcamps_statevector", "gcamps_amplitude", "gcamps_get_tableau", "gcamps_get_bond_dims",
     "gcamps_get_fidelity", "gcamps_get_choice_log", "gcamps_get_site", "gcamps_get_stats",
-    "gcamps_batch_workspace_bytes", "gcamps_batch_run", "gcamps_last_error",
+    "gcamps_batch_workspace_bytes", "gcamps_batch_run", "gcamps_grad_record", "gcamps_grad_loss",
+    "gcamps_grad_gradient", "gcamps_grad_stats", "gcamps_grad_destroy", "gcamps_last_error",
 ]
 
 
@@ -68,6 +69,14 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
                           "(python -m paper_2511_06672_amd.build)")
+    # The library links the system HIP runtime while PyTorch carries its own; the GPU is
+    # found by both only when PyTorch's runtime is initialised first.
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     P, I32, I64, D, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
     sig = {
@@ -92,6 +101,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gcamps_get_stats": [P, C.POINTER(D)],
         "gcamps_batch_workspace_bytes": [C.POINTER(CBatchItem), I32, I32, C.POINTER(SZ)],
         "gcamps_batch_run": [C.POINTER(CBatchItem), I32, P, I32, P, SZ, C.POINTER(D)],
+        "gcamps_grad_record": [C.POINTER(Config), C.POINTER(COp), I64, C.POINTER(I32), C.POINTER(D), I32, P, P,
+                               SZ, P, C.POINTER(P), C.POINTER(D)],
+        "gcamps_grad_loss": [P, C.POINTER(D), C.POINTER(D)],
+        "gcamps_grad_gradient": [P, C.POINTER(D), C.POINTER(D), C.POINTER(D)],
+        "gcamps_grad_stats": [P, C.POINTER(D)],
+        "gcamps_grad_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -295,12 +310,14 @@ def run_circuit(state: State, circuit, phases_override=None):
 def _circuit_ops(circuit, keep: list, phases_override=None):
     """Marshal a workload Circuit into a gcamps_op array (buffers kept alive in `keep`)."""
     ops = []
+    params = []
     for layer in circuit.layers:
         if layer.bricks:
             arr, kw = _words([b.word for b in layer.bricks])
             sites = (C.c_int32 * len(layer.bricks))(*[b.site for b in layer.bricks])
             keep.extend([arr, kw, sites])
             ops.append((OP_CLIFFORD_LAYER, len(layer.bricks), sites, arr, None))
+            params.append(-1)
         for ph in layer.phases:
             phi = ph.phi
             if phases_override is not None and ph.param >= 0:
@@ -309,6 +326,8 @@ def _circuit_ops(circuit, keep: list, phases_override=None):
             a = (C.c_double * circuit.d)(*phi)
             keep.extend([site, a])
             ops.append((OP_PHASE, 1, site, None, a))
+            params.append(ph.param)
+    keep.append(params)
     out = (COp * max(1, len(ops)))()
     for i, (kind, cnt, sites, words, phi) in enumerate(ops):
         out[i].kind = kind
@@ -378,3 +397,73 @@ def batch_run(circuits, cfgs, candset: Optional[CandSet] = None, lanes: int = 4,
     keys = ["circuits", "gates", "wall_ms", "busy_ms", "lanes", "score_ms", "bonds", "tiled_launches",
             "tiled_ms", "tiled_flops"]
     return results, dict(zip(keys, list(st)))
+
+
+class Gradient:
+    """Loss Re sum_j <Z_j> of a parametrised circuit and its gradient (gcamps_grad_*).
+
+    Parameter block b of the circuit (PhaseGate.param == b) uses theta[(d-1)b : (d-1)(b+1)]
+    as (phi_1, ..., phi_{d-1}); decisions are recorded at theta0 and frozen afterwards.
+    """
+
+    def __init__(self, cfg: Config, circuit, candset: Optional[CandSet], theta0, arena_bytes: Optional[int] = None,
+                 device: str = "cuda:0", stream=None):
+        import torch
+        self.cfg = cfg
+        self.d = cfg.d
+        self._keep: list = []
+        self.ops, self.n_ops = _circuit_ops(circuit, self._keep)
+        params = self._keep[-2]
+        self.op_param = (C.c_int32 * max(1, len(params)))(*params)
+        self.n_theta = len(theta0)
+        ctx_bytes = (workspace_bytes(cfg) + 255) & ~255
+        if arena_bytes is None:
+            slot = (cfg.chi_max * cfg.d) ** 2 * cfg.d * 16
+            arena_bytes = min(24 << 30, 96 * (cfg.n + 16) * slot)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(ctx_bytes + arena_bytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        th = (C.c_double * max(1, self.n_theta))(*[float(x) for x in theta0])
+        h = C.c_void_p()
+        loss = C.c_double(0)
+        self._candset = candset
+        _check(lib().gcamps_grad_record(C.byref(cfg), self.ops, self.n_ops, self.op_param, th, self.n_theta,
+                                        candset.handle if candset else None, C.c_void_p(aligned),
+                                        ctx_bytes + arena_bytes, C.c_void_p(self.stream.cuda_stream),
+                                        C.byref(h), C.byref(loss)))
+        self.handle = h
+        self.loss0 = loss.value
+
+    def _theta(self, theta):
+        assert len(theta) == self.n_theta
+        return (C.c_double * max(1, self.n_theta))(*[float(x) for x in theta])
+
+    def loss(self, theta) -> float:
+        out = C.c_double(0)
+        _check(lib().gcamps_grad_loss(self.handle, self._theta(theta), C.byref(out)))
+        return out.value
+
+    def gradient(self, theta):
+        out = C.c_double(0)
+        g = (C.c_double * max(1, self.n_theta))()
+        _check(lib().gcamps_grad_gradient(self.handle, self._theta(theta), C.byref(out), g))
+        return out.value, np.frombuffer(g, dtype=np.float64)[:self.n_theta].copy()
+
+    def stats(self) -> dict:
+        out = (C.c_double * 8)()
+        _check(lib().gcamps_grad_stats(self.handle, out))
+        keys = ["replay_ms", "reverse_ms", "arena_peak_bytes", "tape_steps", "gates", "record_ms",
+                "factorisations", "choices"]
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gcamps_grad_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

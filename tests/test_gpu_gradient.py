@@ -1,0 +1,104 @@
+"""Reverse-mode gradient of Re sum_j <Z_j> (gcamps_grad_*) against the oracle.
+
+* No truncation (chi_max = d^(n/2), cutoff 0): the GCAMPS state is the exact state, so the
+  gradient must equal the dense derivative (oracle.gradient.dense_gradient).
+* Truncated regime: the derivative with frozen decisions; compared with Richardson-
+  extrapolated central differences of the oracle's frozen replay and of the library's own.
+Tolerances: relative to the largest component (infinity norm); central differences with
+step h carry an O(h^2) error plus the replay's rounding divided by h.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+EXACT_TOL = 1e-8      # adjoint vs exact dense derivative (rounding of a few hundred FP64 steps)
+FD_TOL = 1e-6         # adjoint vs Richardson-extrapolated central differences, h = 1e-6:
+                      # O(h^4) truncation, replay rounding (~1e-14) / h ~ 1e-8
+
+
+def theta_of(circuit):
+    items = sorted((ph.param, ph.phi[1:]) for L in circuit.layers for ph in L.phases if ph.param >= 0)
+    return np.array([x for _, phi in items for x in phi])
+
+
+def rel_inf(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def test_gradient_without_truncation_equals_dense_derivative():
+    from oracle.gradient import dense_gradient, dense_loss
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import candidate_words, workload
+    c = workload("grad_d3_n24", n=6).circuit          # 12 layers, 32 parametrised gates
+    th = theta_of(c)
+    cands = candidate_words(3, 24, 902)
+    dense = dense_gradient(c, th)
+    assert np.max(np.abs(dense)) > 1e-2                  # a loss that depends on theta
+    for prec in (0, 1):
+        print(f"[gpu-case] gradient exact regime n=6 prec={prec}", flush=True)
+        cfg = g.make_config(3, 6, 27, 0.0, score_prec=prec, max_candidates=24)
+        gr = g.Gradient(cfg, c, g.CandSet(3, cands), th)
+        assert abs(gr.loss0 - dense_loss(c, th)) < 1e-10
+        assert gr.loss(th) == gr.loss0
+        loss, grad = gr.gradient(th)
+        assert loss == gr.loss0
+        assert rel_inf(grad, dense) < EXACT_TOL
+        gr.close()
+
+
+def test_gradient_with_truncation_matches_oracle_finite_differences():
+    from oracle.gcamps import Config
+    from oracle.gradient import fd_gradient, record
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import candidate_words, workload
+    c = workload("grad_d3_n24", n=8).circuit          # 16 layers, 32 parametrised gates
+    th = theta_of(c)
+    cands = candidate_words(3, 24, 903)
+    ocfg = Config(chi_max=9, cutoff=1e-10)
+    st, frozen = record(c, cands, ocfg, th)
+    assert st.f_est < 0.999
+    print("[gpu-case] gradient truncated regime n=8 chi=9", flush=True)
+    gr = g.Gradient(g.make_config(3, 8, 9, 1e-10, max_candidates=24), c, g.CandSet(3, cands), th)
+    assert abs(gr.loss0 - st.loss_sum_z()) < 1e-10
+    loss, grad = gr.gradient(th)
+    sample = list(range(0, 64, 3))
+    fd = fd_gradient(c, cands, ocfg, th, frozen, h=1e-6, params=sample, richardson=True)
+    assert np.max(np.abs(fd[sample])) > 1e-3
+    assert np.max(np.abs(grad[sample] - fd[sample])) < FD_TOL * np.max(np.abs(grad))
+    # the library's own frozen replay agrees as well (Richardson-extrapolated differences)
+    h = 1e-6
+
+    def central(k, step):
+        e = np.zeros_like(th)
+        e[k] = step
+        return (gr.loss(th + e) - gr.loss(th - e)) / (2 * step)
+
+    for k in (0, 5, 11, 31):
+        fdk = (4 * central(k, h) - central(k, 2 * h)) / 3
+        assert abs(fdk - grad[k]) < FD_TOL * np.max(np.abs(grad))
+    st_ = gr.stats()
+    assert st_["gates"] == 32 and st_["tape_steps"] > 0
+    gr.close()
+
+
+def test_gradient_with_fixed_gates_and_single_site_support():
+    """T gates with fixed angles mixed with parametrised ones; a support of one site
+    (the first gate acts on |0>, where Z_s commutes through the identity Clifford)."""
+    from oracle.gradient import dense_gradient
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import (Circuit, Layer, PhaseGate, brickwork_circuit, candidate_words,
+                                               t_gate_phases)
+    base = brickwork_circuit(3, 6, 3, 6, 904, one_per_layer=False, parametrised=True)
+    layers = [Layer([], [PhaseGate(2, (0.0, 0.4, -1.1), 6)])] + base.layers
+    layers[2].phases.append(PhaseGate(1, t_gate_phases(3)))
+    c = Circuit(3, 6, layers)
+    th = theta_of(c)
+    dense = dense_gradient(c, th)
+    assert np.max(np.abs(dense)) > 1e-2
+    print("[gpu-case] gradient with fixed gates, n=6", flush=True)
+    gr = g.Gradient(g.make_config(3, 6, 27, 0.0, max_candidates=16), c, g.CandSet(3, candidate_words(3, 16, 904)),
+                    th)
+    _, grad = gr.gradient(th)
+    assert rel_inf(grad, dense) < EXACT_TOL
+    gr.close()

@@ -36,9 +36,11 @@ def test_dense_loss_and_gradient_closed_form():
 
 
 def test_dense_gradient_matches_dense_finite_differences():
-    c = brickwork_circuit(3, 4, 6, 4, 701, one_per_layer=False, parametrised=True)
+    from paper_2511_06672_amd.workload import workload
+    c = workload("grad_d3_n24", n=4).circuit
     th = theta_of(c)
     g = dense_gradient(c, th)
+    assert np.max(np.abs(g)) > 1e-2
     h = 1e-5
     fd = np.array([(dense_loss(c, th + h * e) - dense_loss(c, th - h * e)) / (2 * h) for e in np.eye(len(th))])
     assert np.max(np.abs(g - fd)) < 1e-8 * max(1.0, np.max(np.abs(g)))
@@ -53,20 +55,24 @@ def test_frozen_replay_gradient_equals_dense_gradient_without_truncation():
     assert abs(st.loss_sum_z() - dense_loss(c, th)) < 1e-10
     assert replay_loss(c, cands, cfg, th, frozen) == st.loss_sum_z()
     g = dense_gradient(c, th)
+    assert np.max(np.abs(g)) > 1e-2                        # a loss that depends on theta
     fd = fd_gradient(c, cands, cfg, th, frozen, h=1e-5)
     assert np.max(np.abs(fd - g)) <= 1e-7 * np.max(np.abs(g))
 
 
 def test_frozen_replay_in_the_truncated_regime_is_smooth():
-    c = brickwork_circuit(3, 8, 16, 6, 703, one_per_layer=False, parametrised=True)
+    """With decisions frozen, the truncated forward pass is smooth: central differences
+    converge at the O(h^2) rate (halving h divides their change by about four)."""
+    from paper_2511_06672_amd.workload import workload
+    c = workload("grad_d3_n24", n=8).circuit
     th = theta_of(c)
     cands = candidate_words(3, 24, 703)
     cfg = Config(chi_max=9, cutoff=1e-10)
     st, frozen = record(c, cands, cfg, th)
     assert st.f_est < 0.999                       # truncation happened
     assert replay_loss(c, cands, cfg, th, frozen) == st.loss_sum_z()
-    g1 = fd_gradient(c, cands, cfg, th, frozen, h=1e-4, params=[0, 3, 7, 10])
-    g2 = fd_gradient(c, cands, cfg, th, frozen, h=5e-5, params=[0, 3, 7, 10])
     sel = [0, 3, 7, 10]
-    # O(h^2) truncation error: halving h changes the estimate by about 3/4 of its error
-    assert np.max(np.abs(g1[sel] - g2[sel])) < 1e-6 * max(1.0, np.max(np.abs(g2[sel])))
+    g = [fd_gradient(c, cands, cfg, th, frozen, h=h, params=sel)[sel] for h in (1e-4, 5e-5, 2.5e-5)]
+    assert np.max(np.abs(g[2])) > 1e-3            # a loss that depends on theta
+    e1, e2 = np.abs(g[0] - g[1]), np.abs(g[1] - g[2])
+    assert np.all(e2 <= 0.3 * e1 + 1e-9)
