@@ -18,6 +18,12 @@ n_i ~ U{8..48} sites, T_i ~ U{4..60} T gates at uniform positions, 2 n_i layers,
 chi_max = 128, cutoff 1e-10, 512 shared candidates, FP32-scored) on concurrent lanes:
 
     python bench.py --workload batch [--batch-count C] [--lanes L]
+
+A third measures the reverse-mode gradient of Re sum_j <Z_j> with respect to 64 phase
+angles (qutrits, n = 24, 48 layers, 32 parametrised gates, chi_max = 256, cutoff 1e-10,
+512 candidates, FP64 scoring):
+
+    python bench.py --workload grad
 """
 from __future__ import annotations
 
@@ -175,6 +181,95 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def grad_cpu_baseline(c, wl, theta, budget_s):
+    """The oracle's gradient is central differences of its frozen replay (two replays per
+    angle).  Timed on a prefix of the circuit whose recording fits in half the budget and
+    whose bonds stay below 27 before its last layer (identity-only candidate set, so that recording
+    does not score): the gradient rate
+    reported is 1 / (2 * params * prefix replay time), an upper bound for the full circuit."""
+    from oracle.gcamps import Config, Gcamps
+    from oracle.gradient import angles, n_param_gates, record, replay_loss
+    from paper_2511_06672_amd.workload import Circuit
+    ocfg = Config(chi_max=wl.chi_max, cutoff=wl.cutoff, max_sweeps=wl.max_sweeps)
+    ident = [wl.candidates[0]]
+    phis = angles(theta, c.d, n_param_gates(c))
+    orc = Gcamps(c.d, c.n, ocfg, ident)
+    t0 = time.perf_counter()
+    nl = 0
+    for L, layer in enumerate(c.layers):
+        for b in layer.bricks:
+            orc.apply_clifford(b.site, b.word.gens, b.word.weyl)
+        for ph in layer.phases:
+            orc.apply_phase_rotation(ph.site, phis[ph.param])
+        nl = L + 1
+        if layer.phases:
+            log(f"  oracle layer {L + 1}/{len(c.layers)}: {time.perf_counter() - t0:.1f} s, "
+                f"max bond {max(orc.mps.bond_dims())}")
+        # stop before a gate at large bonds could overrun the budget by minutes
+        if time.perf_counter() - t0 > budget_s / 2 or max(orc.mps.bond_dims()) >= 27:
+            break
+    prefix = Circuit(c.d, c.n, c.layers[:nl])
+    _, frozen = record(prefix, ident, ocfg, theta)
+    t1 = time.perf_counter()
+    replay_loss(prefix, ident, ocfg, theta, frozen)
+    t_rep = time.perf_counter() - t1
+    threads = os.environ.get("OPENBLAS_NUM_THREADS") or os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    return {"value": 1.0 / (2 * len(theta) * t_rep), "unit": "gradients/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"frozen replay of the first {nl} of {len(c.layers)} layers ({prefix.n_phase_gates} of "
+                      f"{c.n_phase_gates} gates, identity-only candidate set) in {t_rep:.2f} s; central "
+                      f"differences need {2 * len(theta)} replays (upper bound for the full circuit)"}
+
+
+def main_grad(args):
+    import torch
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import workload
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    wl = workload("grad_d3_n24")
+    c = wl.circuit
+    items = sorted((ph.param, ph.phi[1:]) for L in c.layers for ph in L.phases if ph.param >= 0)
+    theta = np.array([x for _, phi in items for x in phi])
+    cfg = g.make_config(c.d, c.n, wl.chi_max, wl.cutoff, score_prec=g.SCORE_FP64, max_sweeps=wl.max_sweeps,
+                        max_candidates=len(wl.candidates))
+    log(f"gradient workload: n={c.n} layers={len(c.layers)} gates={c.n_phase_gates} params={len(theta)}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gr = g.Gradient(cfg, c, g.CandSet(c.d, wl.candidates), theta)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    log(f"recorded forward pass: {t_rec:.2f} s, loss {gr.loss0:.12f}")
+    for w in range(args.warmup):
+        gr.gradient(theta)
+    t0 = time.perf_counter()
+    loss_r = gr.loss(theta)
+    t_replay = time.perf_counter() - t0
+    times = []
+    for k in range(args.steps):
+        t0 = time.perf_counter()
+        loss, grad = gr.gradient(theta)
+        times.append(time.perf_counter() - t0)
+        log(f"gradient {k + 1}/{args.steps}: {times[-1]:.2f} s, |g|_inf {np.max(np.abs(grad)):.3e}")
+    t = max(times)
+    st = gr.stats()
+    cpu = None if args.no_cpu else grad_cpu_baseline(c, wl, theta, args.cpu_budget)
+    out = {
+        "metric": "reverse-mode gradients/sec of Re sum_j <Z_j> (64 angles, frozen decisions)",
+        "value": 1.0 / t, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * t, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128", "data": "synthetic (seeded brickwork circuit, angles and candidate set)",
+        "config": {"workload": f"qutrit parametrised brickwork d={c.d} n={c.n} layers={len(c.layers)} "
+                               f"gates={c.n_phase_gates} params={len(theta)} chi_max={wl.chi_max} "
+                               f"cutoff={wl.cutoff} candidates={len(wl.candidates)} FP64 scoring",
+                   "parallelism": "1 GPU"},
+        "loss": loss, "replay_loss_equal": bool(loss_r == gr.loss0), "record_ms": 1e3 * t_rec,
+        "replay_ms": 1e3 * t_replay, "gradient_over_replay": t / t_replay, "grad_inf_norm": float(np.max(np.abs(grad))),
+        "arena_peak_gib": st["arena_peak_bytes"] / 2 ** 30, "tape_steps": int(st["tape_steps"]),
+        "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,7 +279,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["headline", "batch"], default="headline")
+    ap.add_argument("--workload", choices=["headline", "batch", "grad"], default="headline")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--serial-check", action="store_true", help="batch: also run on one lane")
@@ -195,6 +290,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         main_batch(args)
+        return
+    if args.workload == "grad":
+        main_grad(args)
         return
 
     import numpy as np

@@ -35,7 +35,8 @@ def angles(theta: Sequence[float], d: int, ngates: int) -> List[Tuple[float, ...
 
 
 def n_param_gates(circuit) -> int:
-    return sum(1 for L in circuit.layers for ph in L.phases if ph.param >= 0)
+    """Number of parameter blocks: one past the largest parameter index in the circuit."""
+    return 1 + max((ph.param for L in circuit.layers for ph in L.phases), default=-1)
 
 
 # ------------------------------------------------------------------ dense definition

@@ -102,3 +102,38 @@ def test_gradient_with_fixed_gates_and_single_site_support():
     _, grad = gr.gradient(th)
     assert rel_inf(grad, dense) < EXACT_TOL
     gr.close()
+
+
+def test_gradient_full_size_against_finite_differences():
+    """The gradient workload at full size (n = 24, 48 layers, 32 gates, chi_max = 256, 512
+    candidates, FP64 scoring), in the configuration the benchmark times.  The oracle cannot
+    replay it in test time, so the property checked is adjoint = derivative of the library's
+    own frozen replay, by Richardson-extrapolated central differences with h = 3e-5 on the
+    largest component and one more.  Tolerance 2e-5 of |g|_inf: the replay's rounding
+    (~1e-13 absolute in L) over 2h gives ~3e-9 absolute, ~6e-6 of |g|_inf ~ 5e-4."""
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import workload
+    wl = workload("grad_d3_n24")
+    c = wl.circuit
+    th = theta_of(c)
+    print("[gpu-case] gradient full size n=24 chi=256: record", flush=True)
+    cfg = g.make_config(3, c.n, wl.chi_max, wl.cutoff, score_prec=0, max_candidates=len(wl.candidates))
+    gr = g.Gradient(cfg, c, g.CandSet(3, wl.candidates), th)
+    print("[gpu-case] gradient full size: reverse sweep", flush=True)
+    loss, grad = gr.gradient(th)
+    assert loss == gr.loss0
+    gmax = np.max(np.abs(grad))
+    assert gmax > 1e-5 and np.all(np.isfinite(grad))
+    order = np.argsort(-np.abs(grad))
+    h = 3e-5
+
+    def central(k, step):
+        e = np.zeros_like(th)
+        e[k] = step
+        return (gr.loss(th + e) - gr.loss(th - e)) / (2 * step)
+
+    for k in (int(order[0]), int(order[7])):
+        print(f"[gpu-case] gradient full size: differences on parameter {k}", flush=True)
+        fd = (4 * central(k, h) - central(k, 2 * h)) / 3
+        assert abs(fd - grad[k]) < 2e-5 * gmax
+    gr.close()
