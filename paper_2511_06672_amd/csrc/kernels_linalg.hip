@@ -200,36 +200,44 @@ __device__ __forceinline__ bool rot_params(double a, double b, double gr, double
 }
 
 // A sequence of parallel Jacobi steps on the Hermitian H (2*half indices, half <= 16) held as
-// two re/im plane pairs in LDS (double buffer).  Step s uses the pairs tab[s][k] = (p, q).  Each
-// thread recomputes the rotation parameters it needs from the old buffer, writes its 2x2 blocks
-// into the new buffer and rotates its eigenvector entries (V planes, in place), so a step
-// needs one barrier.  Returns the index (0/1) of the buffer holding the result; *any is set when
-// a rotation happened.
+// two re/im plane pairs in LDS (double buffer).  Step s uses the pairs tab[s][k] = (p, q).
+// Thread (k1, k2) (k1, k2 < half) owns the 2x2 block of rows (p_k1, q_k1) and columns
+// (p_k2, q_k2): it computes the rotations of pairs k1 and k2 from the old buffer, writes its
+// rotated block into the new buffer, and applies rotation k1 to rows 2 k2 and 2 k2 + 1 of the
+// eigenvector accumulator (V planes, in place; 2 * half rows in total), so a step needs one
+// barrier and every rotation is computed once per thread that uses it.  Returns the index
+// (0/1) of the buffer holding the result; *any is set when a rotation happened.
 __device__ int jacobi_steps(double* __restrict__ h0r, double* __restrict__ h0i, double* __restrict__ h1r,
                             double* __restrict__ h1i, int ldh, int half, const unsigned char* __restrict__ tab,
-                            int nsteps, double* __restrict__ vr, double* __restrict__ vi, int ldv, int vrows,
+                            int nsteps, double* __restrict__ vr, double* __restrict__ vi, int ldv,
                             const JacobiArgs& ja, int* any) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  const float inv_half = 1.0f / (float)half;
+  const int t = threadIdx.x;
+  const bool active = t < half * half;
+  const int k1 = active ? (int)(((float)t + 0.5f) / (float)half) : 0;
+  const int k2 = t - k1 * half;
+  const int v0 = 2 * k2, v1 = 2 * k2 + 1;
   int cur = 0;
   for (int step = 0; step < nsteps; ++step) {
-    const unsigned char* pt = tab + step * 2 * half;
-    const double* ir = cur ? h1r : h0r;
-    const double* ii = cur ? h1i : h0i;
-    double* orr = cur ? h0r : h1r;
-    double* oi = cur ? h0i : h1i;
-    for (int idx = t; idx < half * half; idx += nt) {
-      const int k1 = (int)(((float)idx + 0.5f) * inv_half), k2 = idx - k1 * half;
+    if (active) {
+      const unsigned char* pt = tab + step * 2 * half;
+      const double* __restrict__ ir = cur ? h1r : h0r;
+      const double* __restrict__ ii = cur ? h1i : h0i;
+      double* __restrict__ orr = cur ? h0r : h1r;
+      double* __restrict__ oi = cur ? h0i : h1i;
       const int p1 = pt[2 * k1], q1 = pt[2 * k1 + 1], p2 = pt[2 * k2], q2 = pt[2 * k2 + 1];
-      double c1, s1, pr1, pi1, na1, nb1, c2, s2, pr2, pi2, na2, nb2;
-      const bool f1 = rot_params(ir[p1 * ldh + p1], ir[q1 * ldh + q1], ir[p1 * ldh + q1], ii[p1 * ldh + q1], ja, c1, s1,
-                                 pr1, pi1, na1, nb1);
-      const bool f2 = rot_params(ir[p2 * ldh + p2], ir[q2 * ldh + q2], ir[p2 * ldh + q2], ii[p2 * ldh + q2], ja, c2, s2,
-                                 pr2, pi2, na2, nb2);
+      const double a1 = ir[p1 * ldh + p1], b1 = ir[q1 * ldh + q1], g1r = ir[p1 * ldh + q1], g1i = ii[p1 * ldh + q1];
+      const double a2 = ir[p2 * ldh + p2], b2 = ir[q2 * ldh + q2], g2r = ir[p2 * ldh + q2], g2i = ii[p2 * ldh + q2];
       double ar = ir[p1 * ldh + p2], ai = ii[p1 * ldh + p2];
       double br = ir[p1 * ldh + q2], bi = ii[p1 * ldh + q2];
       double cr = ir[q1 * ldh + p2], ci = ii[q1 * ldh + p2];
       double dr = ir[q1 * ldh + q2], di = ii[q1 * ldh + q2];
+      const double w0pr = vr[v0 * ldv + p1], w0pi = vi[v0 * ldv + p1];
+      const double w0qr = vr[v0 * ldv + q1], w0qi = vi[v0 * ldv + q1];
+      const double w1pr = vr[v1 * ldv + p1], w1pi = vi[v1 * ldv + p1];
+      const double w1qr = vr[v1 * ldv + q1], w1qi = vi[v1 * ldv + q1];
+      double c1, s1, pr1, pi1, na1, nb1, c2, s2, pr2, pi2, na2, nb2;
+      const bool f1 = rot_params(a1, b1, g1r, g1i, ja, c1, s1, pr1, pi1, na1, nb1);
+      const bool f2 = rot_params(a2, b2, g2r, g2i, ja, c2, s2, pr2, pi2, na2, nb2);
       if (f1) {  // rows: r_p' = c r_p - s ph r_q ; r_q' = s r_p + c ph r_q
         const double xr = pr1 * cr - pi1 * ci, xi = pr1 * ci + pi1 * cr;
         const double yr = pr1 * dr - pi1 * di, yi = pr1 * di + pi1 * dr;
@@ -273,21 +281,20 @@ __device__ int jacobi_steps(double* __restrict__ h0r, double* __restrict__ h0i, 
       oi[q1 * ldh + p2] = ci;
       orr[q1 * ldh + q2] = dr;
       oi[q1 * ldh + q2] = di;
-    }
-    for (int idx = t; idx < vrows * half; idx += nt) {
-      const int row = (int)(((float)idx + 0.5f) * inv_half), k = idx - row * half;
-      const int p = pt[2 * k], q = pt[2 * k + 1];
-      double c, sn, pr, pi, na, nb;
-      if (!rot_params(ir[p * ldh + p], ir[q * ldh + q], ir[p * ldh + q], ii[p * ldh + q], ja, c, sn, pr, pi, na, nb))
-        continue;
-      pi = -pi;
-      const double apr = vr[row * ldv + p], api = vi[row * ldv + p];
-      const double aqr = vr[row * ldv + q], aqi = vi[row * ldv + q];
-      const double xr = pr * aqr - pi * aqi, xi = pr * aqi + pi * aqr;
-      vr[row * ldv + p] = c * apr - sn * xr;
-      vi[row * ldv + p] = c * api - sn * xi;
-      vr[row * ldv + q] = sn * apr + c * xr;
-      vi[row * ldv + q] = sn * api + c * xi;
+      if (f1) {  // V columns (p1, q1), rows v0, v1: v_p' = c v_p - s conj(ph) v_q ; v_q' = s v_p + c conj(ph) v_q
+        const double pr = pr1, pi = -pi1;
+        double xr = pr * w0qr - pi * w0qi, xi = pr * w0qi + pi * w0qr;
+        vr[v0 * ldv + p1] = c1 * w0pr - s1 * xr;
+        vi[v0 * ldv + p1] = c1 * w0pi - s1 * xi;
+        vr[v0 * ldv + q1] = s1 * w0pr + c1 * xr;
+        vi[v0 * ldv + q1] = s1 * w0pi + c1 * xi;
+        xr = pr * w1qr - pi * w1qi;
+        xi = pr * w1qi + pi * w1qr;
+        vr[v1 * ldv + p1] = c1 * w1pr - s1 * xr;
+        vi[v1 * ldv + p1] = c1 * w1pi - s1 * xi;
+        vr[v1 * ldv + q1] = s1 * w1pr + c1 * xr;
+        vi[v1 * ldv + q1] = s1 * w1pi + c1 * xi;
+      }
     }
     __syncthreads();
     cur ^= 1;
@@ -345,7 +352,7 @@ __global__ __launch_bounds__(256) void k_jacobi_small(const z64* __restrict__ G,
     __syncthreads();
     // an odd number of steps swaps the buffers; keep the live matrix in (h0)
     const int res = jacobi_steps(cur ? h1r : h0r, cur ? h1i : h0i, cur ? h0r : h1r, cur ? h0i : h1i, ldh, half, tab,
-                                 mp - 1, vr, vi, ldh, mp, ja, &any);
+                                 mp - 1, vr, vi, ldh, ja, &any);
     cur ^= res;
     ++sweeps;
     __syncthreads();
@@ -418,7 +425,7 @@ __global__ __launch_bounds__(256) void k_jblock_solve(const z64* __restrict__ Gp
   __syncthreads();
   const int run = need;
   if (run) {
-    jacobi_steps(h0r, h0i, h1r, h1i, SLD, BJ, tab, full ? BJ2 - 1 : BJ, vr, vi, SLD, BJ2, ja, &any);
+    jacobi_steps(h0r, h0i, h1r, h1i, SLD, BJ, tab, full ? BJ2 - 1 : BJ, vr, vi, SLD, ja, &any);
     z64* vo = Vout + (size_t)k * BJ2 * BJ2;
     for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
       const int i = idx / BJ2, j = idx % BJ2;
