@@ -166,36 +166,35 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return y * (2.0 - x * y);
 }
 
-// Rotation for the Hermitian 2x2 [[a, g], [conj g, b]]: J = [[c, s], [-s conj(ph), c conj(ph)]]
-// with ph = g/|g| zeroes the off-diagonal; the new diagonal is (a - t|g|, b + t|g|), where
-// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (b - a) / (2|g|), c = 1/sqrt(1+t^2), s = c t.
-__device__ __forceinline__ bool rot_params(double a, double b, double gr, double gi, const JacobiArgs& ja, double& c,
-                                           double& s, double& pr, double& pi, double& na, double& nb) {
+// Whether the pair with diagonal (a, b) and off-diagonal g = gr + i gi is rotated.
+__device__ __forceinline__ bool rot_needed(double a, double b, double gr, double gi, const JacobiArgs& ja) {
   const double h2 = gr * gr + gi * gi;
-  bool doit;
-  if (ja.rel)
-    doit = h2 > 1e-290 && h2 > ja.tol * ja.tol * fabs(a) * fabs(b) && fmax(fabs(a), fabs(b)) > ja.skip;
-  else
-    doit = h2 > 1e-290 && h2 > ja.thr * ja.thr;
-  if (!doit) return false;
-  const double inv_h = rsqrt_nr(h2);
-  const double h = h2 * inv_h;
-  const double zeta = 0.5 * (b - a) * inv_h;
-  const double az = fabs(zeta);
-  double t;
-  if (az > 1e150) {
-    t = 0.5 * rcp_nr(zeta);
-  } else {
-    const double q = 1.0 + zeta * zeta;
-    t = rcp_nr(az + q * rsqrt_nr(q));
-    if (zeta < 0) t = -t;
-  }
-  c = rsqrt_nr(1.0 + t * t);
-  s = c * t;
-  pr = gr * inv_h;
-  pi = gi * inv_h;
-  na = a - t * h;
-  nb = b + t * h;
+  if (ja.rel) return h2 > 1e-290 && h2 > ja.tol * ja.tol * fabs(a) * fabs(b) && fmax(fabs(a), fabs(b)) > ja.skip;
+  return h2 > 1e-290 && h2 > ja.thr * ja.thr;
+}
+
+// Rotation J = [[c, -sp], [conj(sp), c]] (c real, |sp|^2 = 1 - c^2) for the Hermitian 2x2
+// [[a, g], [conj g, b]]: J H J^H is diagonal with entries (a - t|g|, b + t|g|), where
+// t = sign(b - a) 2|g| / (|b - a| + R), R = sqrt((b - a)^2 + 4|g|^2) (the smaller root of
+// |g| t^2 - (a - b) t - |g| = 0), c = 1/sqrt(1 + t^2) and sp = c t g/|g|.  With
+// den = |b - a| + R these are c = den / sqrt(den^2 + 4|g|^2), sp = sign 2 g / sqrt(den^2 + 4|g|^2),
+// t|g| = sign 2|g|^2 / den: two reciprocal square roots in sequence.
+__device__ __forceinline__ bool rot_params(double a, double b, double gr, double gi, const JacobiArgs& ja, double& c,
+                                           double& spr, double& spi, double& na, double& nb) {
+  if (!rot_needed(a, b, gr, gi, ja)) return false;
+  const double h2 = gr * gr + gi * gi;
+  const double dlt = b - a;
+  const double sg = dlt < 0.0 ? -1.0 : 1.0;
+  const double r2 = dlt * dlt + 4.0 * h2;
+  const double den = fabs(dlt) + r2 * rsqrt_nr(r2);
+  const double q = rsqrt_nr(den * den + 4.0 * h2);
+  c = den * q;
+  const double f = 2.0 * sg * q;
+  spr = f * gr;
+  spi = f * gi;
+  const double th = 2.0 * sg * h2 * rcp_nr(den);
+  na = a - th;
+  nb = b + th;
   return true;
 }
 
@@ -235,37 +234,36 @@ __device__ int jacobi_steps(double* __restrict__ h0r, double* __restrict__ h0i, 
       const double w0qr = vr[v0 * ldv + q1], w0qi = vi[v0 * ldv + q1];
       const double w1pr = vr[v1 * ldv + p1], w1pi = vi[v1 * ldv + p1];
       const double w1qr = vr[v1 * ldv + q1], w1qi = vi[v1 * ldv + q1];
-      double c1, s1, pr1, pi1, na1, nb1, c2, s2, pr2, pi2, na2, nb2;
-      const bool f1 = rot_params(a1, b1, g1r, g1i, ja, c1, s1, pr1, pi1, na1, nb1);
-      const bool f2 = rot_params(a2, b2, g2r, g2i, ja, c2, s2, pr2, pi2, na2, nb2);
-      if (f1) {  // rows: r_p' = c r_p - s ph r_q ; r_q' = s r_p + c ph r_q
-        const double xr = pr1 * cr - pi1 * ci, xi = pr1 * ci + pi1 * cr;
-        const double yr = pr1 * dr - pi1 * di, yi = pr1 * di + pi1 * dr;
-        const double nar = c1 * ar - s1 * xr, nai = c1 * ai - s1 * xi;
-        const double nbr = c1 * br - s1 * yr, nbi = c1 * bi - s1 * yi;
-        cr = s1 * ar + c1 * xr;
-        ci = s1 * ai + c1 * xi;
-        dr = s1 * br + c1 * yr;
-        di = s1 * bi + c1 * yi;
+      double c1, sp1r, sp1i, na1, nb1, c2, sp2r, sp2i, na2, nb2;
+      const bool f1 = rot_params(a1, b1, g1r, g1i, ja, c1, sp1r, sp1i, na1, nb1);
+      const bool f2 = rot_params(a2, b2, g2r, g2i, ja, c2, sp2r, sp2i, na2, nb2);
+      if (f1) {  // rows: r_p' = c r_p - sp r_q ; r_q' = conj(sp) r_p + c r_q
+        const double nar = c1 * ar - (sp1r * cr - sp1i * ci), nai = c1 * ai - (sp1r * ci + sp1i * cr);
+        const double nbr = c1 * br - (sp1r * dr - sp1i * di), nbi = c1 * bi - (sp1r * di + sp1i * dr);
+        const double ncr = c1 * cr + (sp1r * ar + sp1i * ai), nci = c1 * ci + (sp1r * ai - sp1i * ar);
+        const double ndr = c1 * dr + (sp1r * br + sp1i * bi), ndi = c1 * di + (sp1r * bi - sp1i * br);
         ar = nar;
         ai = nai;
         br = nbr;
         bi = nbi;
-      }
-      if (f2) {  // cols: c_p' = c c_p - s conj(ph) c_q ; c_q' = s c_p + c conj(ph) c_q
-        const double pr = pr2, pi = -pi2;
-        const double xr = pr * br - pi * bi, xi = pr * bi + pi * br;
-        const double yr = pr * dr - pi * di, yi = pr * di + pi * dr;
-        const double nar = c2 * ar - s2 * xr, nai = c2 * ai - s2 * xi;
-        const double ncr = c2 * cr - s2 * yr, nci = c2 * ci - s2 * yi;
-        br = s2 * ar + c2 * xr;
-        bi = s2 * ai + c2 * xi;
-        dr = s2 * cr + c2 * yr;
-        di = s2 * ci + c2 * yi;
-        ar = nar;
-        ai = nai;
         cr = ncr;
         ci = nci;
+        dr = ndr;
+        di = ndi;
+      }
+      if (f2) {  // cols: c_p' = c c_p - conj(sp) c_q ; c_q' = sp c_p + c c_q
+        const double nar = c2 * ar - (sp2r * br + sp2i * bi), nai = c2 * ai - (sp2r * bi - sp2i * br);
+        const double ncr = c2 * cr - (sp2r * dr + sp2i * di), nci = c2 * ci - (sp2r * di - sp2i * dr);
+        const double nbr = c2 * br + (sp2r * ar - sp2i * ai), nbi = c2 * bi + (sp2r * ai + sp2i * ar);
+        const double ndr = c2 * dr + (sp2r * cr - sp2i * ci), ndi = c2 * di + (sp2r * ci + sp2i * cr);
+        ar = nar;
+        ai = nai;
+        br = nbr;
+        bi = nbi;
+        cr = ncr;
+        ci = nci;
+        dr = ndr;
+        di = ndi;
       }
       if (k1 == k2 && f1) {
         ar = na1;
@@ -281,19 +279,15 @@ __device__ int jacobi_steps(double* __restrict__ h0r, double* __restrict__ h0i, 
       oi[q1 * ldh + p2] = ci;
       orr[q1 * ldh + q2] = dr;
       oi[q1 * ldh + q2] = di;
-      if (f1) {  // V columns (p1, q1), rows v0, v1: v_p' = c v_p - s conj(ph) v_q ; v_q' = s v_p + c conj(ph) v_q
-        const double pr = pr1, pi = -pi1;
-        double xr = pr * w0qr - pi * w0qi, xi = pr * w0qi + pi * w0qr;
-        vr[v0 * ldv + p1] = c1 * w0pr - s1 * xr;
-        vi[v0 * ldv + p1] = c1 * w0pi - s1 * xi;
-        vr[v0 * ldv + q1] = s1 * w0pr + c1 * xr;
-        vi[v0 * ldv + q1] = s1 * w0pi + c1 * xi;
-        xr = pr * w1qr - pi * w1qi;
-        xi = pr * w1qi + pi * w1qr;
-        vr[v1 * ldv + p1] = c1 * w1pr - s1 * xr;
-        vi[v1 * ldv + p1] = c1 * w1pi - s1 * xi;
-        vr[v1 * ldv + q1] = s1 * w1pr + c1 * xr;
-        vi[v1 * ldv + q1] = s1 * w1pi + c1 * xi;
+      if (f1) {  // V columns (p1, q1), rows v0, v1: v_p' = c v_p - conj(sp) v_q ; v_q' = sp v_p + c v_q
+        vr[v0 * ldv + p1] = c1 * w0pr - (sp1r * w0qr + sp1i * w0qi);
+        vi[v0 * ldv + p1] = c1 * w0pi - (sp1r * w0qi - sp1i * w0qr);
+        vr[v0 * ldv + q1] = c1 * w0qr + (sp1r * w0pr - sp1i * w0pi);
+        vi[v0 * ldv + q1] = c1 * w0qi + (sp1r * w0pi + sp1i * w0pr);
+        vr[v1 * ldv + p1] = c1 * w1pr - (sp1r * w1qr + sp1i * w1qi);
+        vi[v1 * ldv + p1] = c1 * w1pi - (sp1r * w1qi - sp1i * w1qr);
+        vr[v1 * ldv + q1] = c1 * w1qr + (sp1r * w1pr - sp1i * w1pi);
+        vi[v1 * ldv + q1] = c1 * w1qi + (sp1r * w1pi + sp1i * w1pr);
       }
     }
     __syncthreads();
@@ -417,9 +411,7 @@ __global__ __launch_bounds__(256) void k_jblock_solve(const z64* __restrict__ Gp
   for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
     const int i = idx / BJ2, j = idx % BJ2;
     if (i < j && (full || (i < BJ && j >= BJ))) {
-      double c, s, pr, pi, na, nb2;
-      if (rot_params(h0r[i * SLD + i], h0r[j * SLD + j], h0r[i * SLD + j], h0i[i * SLD + j], ja, c, s, pr, pi, na, nb2))
-        need = 1;
+      if (rot_needed(h0r[i * SLD + i], h0r[j * SLD + j], h0r[i * SLD + j], h0i[i * SLD + j], ja)) need = 1;
     }
   }
   __syncthreads();
