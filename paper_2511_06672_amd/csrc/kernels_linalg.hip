@@ -457,7 +457,8 @@ __device__ __forceinline__ int pair_index(int P, int i, int step, int nb) {
   return i < BJ ? I * BJ + i : J * BJ + (i - BJ);
 }
 
-// Kernel B: tiles (P, Q) of G <- V_P^H G V_Q and row tiles of U <- U V_Q (32x32 tiles).
+// Kernel B: tiles (P, Q), P <= Q, of G <- V_P^H G V_Q (the (Q, P) tile is written as the conjugate
+// transpose) and row tiles of U <- U V_Q (32x32 tiles).
 __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64* __restrict__ Up, int mp, int nb,
                                                       int step, const z64* __restrict__ V,
                                                       const int* __restrict__ pair_flag) {
@@ -467,14 +468,19 @@ __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64*
   double* b_re = a_im + BJ2 * SLD;
   double* b_im = b_re + BJ2 * SLD;
   const int half = nb / 2;
-  const int ngt = half * half;
+  const int ngt = half * (half + 1) / 2;  // G tiles (P, Q) with P <= Q; (Q, P) is the mirror
   const int t = threadIdx.x, nt = blockDim.x;
   const int lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
   int tile = blockIdx.x;
   d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
   if (tile < ngt) {
-    const int P = tile / half, Q = tile % half;
+    int P = 0, rem = tile;
+    while (rem >= half - P) {
+      rem -= half - P;
+      ++P;
+    }
+    const int Q = P + rem;
     const int fP = pair_flag[P], fQ = pair_flag[Q];
     if (!fP && !fQ) return;
     const z64* VP = V + (size_t)P * BJ2 * BJ2;
@@ -509,7 +515,9 @@ __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64*
     mm32(a_re, a_im, b_re, b_im, true, accr, acci);  // Y = V_P^H X
     for (int q = 0; q < 4; ++q) {
       const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
-      Gp[(size_t)pair_index(P, row, step, nb) * mp + pair_index(Q, col, step, nb)] = z64{accr[q], acci[q]};
+      const int gr = pair_index(P, row, step, nb), gc = pair_index(Q, col, step, nb);
+      Gp[(size_t)gr * mp + gc] = z64{accr[q], acci[q]};
+      if (P != Q) Gp[(size_t)gc * mp + gr] = z64{accr[q], -acci[q]};
     }
   } else {
     tile -= ngt;
@@ -797,7 +805,7 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
       hipLaunchKernelGGL(k_jblock_solve, dim3(half), dim3(256), 0, s, Gp, mp, nb, step, thr, tol, skipv, rel, w.V,
                          w.flags + 1, w.flags);
       GC_LAUNCH_CHECK();
-      int tiles = half * half + (mp / BJ2) * half;
+      int tiles = half * (half + 1) / 2 + (mp / BJ2) * half;
       hipLaunchKernelGGL(k_jblock_apply, dim3(tiles), dim3(256), lds_b, s, Gp, Up, mp, nb, step, w.V, w.flags + 1);
       GC_LAUNCH_CHECK();
     }
