@@ -311,8 +311,10 @@ __global__ __launch_bounds__(256) void k_gram_purity(int m, int k, const cx<T>* 
   const int nt = (m + TT - 1) / TT;
   int I, J;
   tile_pair(blockIdx.x, nt, I, J);
-  __shared__ T As[2][KC][PAD];
-  __shared__ T Bs[2][KC][PAD];
+  // two LDS stages: chunk c + 1 is fetched into registers while chunk c is multiplied,
+  // then stored into the other stage; one barrier per chunk
+  __shared__ T As[2][2][KC][PAD];
+  __shared__ T Bs[2][2][KC][PAD];
   __shared__ double red[256];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * (TT / 2), wc = (w & 1) * (TT / 2);
@@ -324,32 +326,49 @@ __global__ __launch_bounds__(256) void k_gram_purity(int m, int k, const cx<T>* 
         acci[i][j][q] = T(0);
       }
   const int r0 = I * TT, q0 = J * TT;
-  for (int k0 = 0; k0 < k; k0 += KC) {
+  constexpr int U = TT * KC / 256;
+  cx<T> pa[U], pb[U];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < TT * KC / 256; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int e = t + 256 * u;
       const int row = e >> 4, kk = e & 15;
       const int col = k0 + kk;
-      cx<T> va = {T(0), T(0)}, vb = {T(0), T(0)};
+      pa[u] = cx<T>{T(0), T(0)};
+      pb[u] = cx<T>{T(0), T(0)};
       if (col < k) {
-        if (r0 + row < m) va = N[(size_t)(r0 + row) * k + col];
-        if (q0 + row < m) vb = N[(size_t)(q0 + row) * k + col];
+        if (r0 + row < m) pa[u] = N[(size_t)(r0 + row) * k + col];
+        if (q0 + row < m) pb[u] = N[(size_t)(q0 + row) * k + col];
       }
-      As[0][kk][row] = va.re;
-      As[1][kk][row] = va.im;
-      Bs[0][kk][row] = vb.re;
-      Bs[1][kk][row] = -vb.im;
     }
-    __syncthreads();
+  };
+  auto stash = [&](int sg) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = t + 256 * u;
+      const int row = e >> 4, kk = e & 15;
+      As[sg][0][kk][row] = pa[u].re;
+      As[sg][1][kk][row] = pa[u].im;
+      Bs[sg][0][kk][row] = pb[u].re;
+      Bs[sg][1][kk][row] = -pb[u].im;
+    }
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int sg = 0;
+  for (int k0 = 0; k0 < k; k0 += KC) {
+    const bool more = k0 + KC < k;
+    if (more) fetch(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int ka = kk + (lane >> 4);
       T ar[BL], ai[BL], br[BL], bi[BL];
       for (int i = 0; i < BL; ++i) {
-        ar[i] = As[0][ka][wr + i * 16 + (lane & 15)];
-        ai[i] = As[1][ka][wr + i * 16 + (lane & 15)];
-        br[i] = Bs[0][ka][wc + i * 16 + (lane & 15)];
-        bi[i] = Bs[1][ka][wc + i * 16 + (lane & 15)];
+        ar[i] = As[sg][0][ka][wr + i * 16 + (lane & 15)];
+        ai[i] = As[sg][1][ka][wr + i * 16 + (lane & 15)];
+        br[i] = Bs[sg][0][ka][wc + i * 16 + (lane & 15)];
+        bi[i] = Bs[sg][1][ka][wc + i * 16 + (lane & 15)];
       }
       for (int i = 0; i < BL; ++i)
         for (int j = 0; j < BL; ++j) {
@@ -359,7 +378,9 @@ __global__ __launch_bounds__(256) void k_gram_purity(int m, int k, const cx<T>* 
           acci[i][j] = mfma_t(ai[i], br[j], acci[i][j]);
         }
     }
+    if (more) stash(sg ^ 1);
     __syncthreads();
+    sg ^= 1;
   }
   double pur = 0.0, tr = 0.0;
   const double wgt = (I == J) ? 1.0 : 2.0;
