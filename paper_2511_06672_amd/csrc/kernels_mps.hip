@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256) void k_gram_purity(int m, int k, const cx<T>* 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = t + 256 * u;
-      const int row = e >> 4, kk = e & 15;
+      const int row = e / KC, kk = e % KC;
       const int col = k0 + kk;
       pa[u] = cx<T>{T(0), T(0)};
       pb[u] = cx<T>{T(0), T(0)};
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) void k_gram_purity(int m, int k, const cx<T>* 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = t + 256 * u;
-      const int row = e >> 4, kk = e & 15;
+      const int row = e / KC, kk = e % KC;
       As[sg][0][kk][row] = pa[u].re;
       As[sg][1][kk][row] = pa[u].im;
       Bs[sg][0][kk][row] = pb[u].re;
