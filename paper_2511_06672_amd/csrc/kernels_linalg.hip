@@ -485,6 +485,15 @@ __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64*
     if (!fP && !fQ) return;
     const z64* VP = V + (size_t)P * BJ2 * BJ2;
     const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
+    // V_P is needed after the first product: fetch it into registers now
+    constexpr int PER = BJ2 * BJ2 / 256;
+    z64 vp[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = t + 256 * u;
+      const int r = idx / BJ2, c = idx % BJ2;
+      vp[u] = fP ? VP[idx] : ((r == c) ? z64{1.0, 0.0} : z64{0.0, 0.0});
+    }
     // a[kk][row] = T[row][kk] = G[rows(P)[row], cols(Q)[kk]];  b = V_Q (or identity)
     for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
       const int row = idx / BJ2, kk = idx % BJ2;
@@ -505,11 +514,12 @@ __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64*
       accr[q] = 0.0;
       acci[q] = 0.0;
     }
-    for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = t + 256 * u;
       const int r = idx / BJ2, c = idx % BJ2;
-      const z64 p = fP ? VP[idx] : ((r == c) ? z64{1.0, 0.0} : z64{0.0, 0.0});
-      a_re[r * SLD + c] = p.re;
-      a_im[r * SLD + c] = p.im;
+      a_re[r * SLD + c] = vp[u].re;
+      a_im[r * SLD + c] = vp[u].im;
     }
     __syncthreads();
     mm32(a_re, a_im, b_re, b_im, true, accr, acci);  // Y = V_P^H X
