@@ -24,6 +24,11 @@ angles (qutrits, n = 24, 48 layers, 32 parametrised gates, chi_max = 256, cutoff
 512 candidates, FP64 scoring):
 
     python bench.py --workload grad
+
+A plain device copy of known size calibrates the HBM counters (FETCH_SIZE, WRITE_SIZE)
+used for the roofline's traffic figure:
+
+    python bench.py --workload copy
 """
 from __future__ import annotations
 
@@ -270,6 +275,23 @@ def main_grad(args):
     print(json.dumps(out), flush=True)
 
 
+def main_copy(args):
+    """Plain device-to-device copies of a known size (counter calibration)."""
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    nbytes = 1 << 30
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"workload": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "copies": args.steps, "GB_per_s": 2 * nbytes / dt / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,7 +301,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["headline", "batch", "grad"], default="headline")
+    ap.add_argument("--workload", choices=["headline", "batch", "grad", "copy"], default="headline")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--serial-check", action="store_true", help="batch: also run on one lane")
@@ -293,6 +315,9 @@ def main():
         return
     if args.workload == "grad":
         main_grad(args)
+        return
+    if args.workload == "copy":
+        main_copy(args)
         return
 
     import numpy as np

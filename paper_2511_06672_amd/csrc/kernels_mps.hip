@@ -304,13 +304,19 @@ __global__ __launch_bounds__(256) void k_gram_purity(int m, int k, const cx<T>* 
                                                      double* __restrict__ partial) {
   typedef typename AccT<T>::type acc_t;
   constexpr int TT = 32 * BL, KC = 16, PAD = TT + 4;
-  const int ls = blockIdx.y;
+  // XCD-aware order: workgroup L runs on XCD L mod 8, so the ntp tiles of one candidate are
+  // given consecutive slots of one XCD and share its L2 (candidates are padded to a multiple
+  // of 8; the padding exits at once).
+  const int L = blockIdx.x;
+  const int xcd = L & 7, xslot = L >> 3;
+  const int cg = xslot / ntp, tile = xslot - cg * ntp;
+  const int ls = cg * 8 + xcd;
   const int slot = c0 + ls;
   if (ls >= cnt || (nlimit && slot >= *nlimit)) return;
   const cx<T>* N = nbase + (size_t)ls * stride;
   const int nt = (m + TT - 1) / TT;
   int I, J;
-  tile_pair(blockIdx.x, nt, I, J);
+  tile_pair(tile, nt, I, J);
   // two LDS stages: chunk c + 1 is fetched into registers while chunk c is multiplied,
   // then stored into the other stage; one barrier per chunk
   __shared__ T As[2][2][KC][PAD];
@@ -398,8 +404,8 @@ __global__ __launch_bounds__(256) void k_gram_purity(int m, int k, const cx<T>* 
   pur = block_sum(pur, red);
   tr = block_sum(tr, red);
   if (t == 0) {
-    partial[((size_t)slot * ntp + blockIdx.x) * 2 + 0] = pur;
-    partial[((size_t)slot * ntp + blockIdx.x) * 2 + 1] = tr;
+    partial[((size_t)slot * ntp + tile) * 2 + 0] = pur;
+    partial[((size_t)slot * ntp + tile) * 2 + 1] = tr;
   }
 }
 
@@ -635,7 +641,7 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
   const dim3 ggen(blocks_for((size_t)chil * chir, 256), chunk);
   for (int c0 = 0; c0 < count; c0 += chunk) {
     const int cnt = std::min(chunk, count - c0);
-    const dim3 gg(ggen.x, cnt), gp(ntp, cnt);
+    const dim3 gg(ggen.x, cnt), gp((unsigned)ntp * ((cnt + 7) / 8) * 8);
     const int ev = (evs && evused && 2 * (*evused) + 1 < evcap) ? 2 * (*evused) : -1;
     if (prec == GCAMPS_SCORE_FP64) {
       z64* nb = reinterpret_cast<z64*>(nbuf);
