@@ -52,6 +52,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_gram_purity_f32_headline_d3_n32_traffic.md")
+SCORING_SOURCE = os.path.join(ROOT, "paper_2511_06672_amd", "csrc", "kernels_mps.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the Gram-purity kernel from the committed counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(SCORING_SOURCE, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    want = None
+    value = None
+    for line in text.splitlines():
+        if line.startswith("kernels_mps.hip sha256 prefix at measurement:"):
+            want = line.split(":")[1].strip()
+        if line.startswith("traffic_bytes_per_launch:"):
+            value = float(line.split(":")[1])
+    return value if (want == src and value is not None) else None
+
+
 def run_circuit(g, wl, prec, progress=True):
     import torch
     c = wl.circuit
@@ -366,7 +389,9 @@ def main():
         per_launch_ms = tiled_ms / s32["tiled_launches"]
         achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(),
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE, copy-calibrated)",
+                "algorithmic_bytes": s32["tiled_bytes"] / s32["tiled_launches"],
                 "kernel": "k_gram_purity<float, 4>", "launches": int(s32["tiled_launches"]),
                 "avg_ms": per_launch_ms}
 

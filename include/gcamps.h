@@ -185,7 +185,8 @@ int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap,
  * kernel time in ms, [10] scoring calls (bonds x passes), [11] launches of the Gram-purity MFMA
  * kernel (full-set scoring), [12] their summed kernel time in ms (device events around each
  * launch), [13] their algorithmic flops (4 m^2 k per candidate), [14] bond splits that factorised only the
- * centre tensor (identity kept), [15] reserved (0). */
+ * centre tensor (identity kept), [15] algorithmic bytes read by the Gram-purity launches (each
+ * rotated m x k matrix once). */
 int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[16]);
 
 /* ---------------------------------------------------------------------------

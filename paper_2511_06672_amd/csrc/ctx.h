@@ -502,6 +502,7 @@ struct gcamps_ctx {
             }
             stats[11] += gram_used;
             stats[13] += (double)ncand * 4.0 * mm * mm * kk;
+            stats[15] += (double)ncand * mm * kk * (prec == GCAMPS_SCORE_FP64 ? 16.0 : 8.0);
           }
           stats[1] += 1;
           if (prec != GCAMPS_SCORE_FP64) {

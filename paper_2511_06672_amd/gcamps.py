@@ -290,7 +290,7 @@ class State:
         _check(lib().gcamps_get_stats(self.handle, out))
         keys = ["gates", "bonds_scored", "rescored", "degenerate_cuts", "score_flops",
                 "factor_flops", "score_ms", "host_ms", "rescore_flops", "rescore_ms",
-                "score_launches", "tiled_launches", "tiled_ms", "tiled_flops", "centre_splits", "r15"]
+                "score_launches", "tiled_launches", "tiled_ms", "tiled_flops", "centre_splits", "tiled_bytes"]
         return dict(zip(keys, list(out)))
 
 
