@@ -44,6 +44,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 NEAR_TIE = 1e-4
 
@@ -328,6 +329,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--serial-check", action="store_true", help="batch: also run on one lane")
+    ap.add_argument("--score", choices=["fp32", "bf16"], default="fp32",
+                    help="headline: precision of the timed path's candidate scoring")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -355,15 +358,17 @@ def main():
     log(f"workload {wl.name}: d={c.d} n={c.n} layers={len(c.layers)} gates={ngates} "
         f"chi_max={wl.chi_max} candidates={len(wl.candidates)}")
 
+    prec = g.SCORE_BF16 if args.score == "bf16" else g.SCORE_FP32
+    pname = "split-BF16-scored" if prec == g.SCORE_BF16 else "FP32-scored"
     for w in range(args.warmup):
         log(f"warmup {w + 1}/{args.warmup}")
-        run_circuit(g, wl, g.SCORE_FP32)
+        run_circuit(g, wl, prec)
 
     torch.cuda.synchronize()
     times32, st32 = [], None
     for k in range(args.steps):
-        log(f"timed step {k + 1}/{args.steps} (FP32-scored path)")
-        st32, t = run_circuit(g, wl, g.SCORE_FP32)
+        log(f"timed step {k + 1}/{args.steps} ({pname} path)")
+        st32, t = run_circuit(g, wl, prec)
         times32.append(t)
     t32 = max(times32)   # one rank: max over ranks is this rank
     s32 = st32.stats()
@@ -381,19 +386,24 @@ def main():
                  "fidelity_rel_diff": abs(f32 - f64) / f64,
                  "equal_final_fidelity": bool(same_choices and abs(f32 - f64) <= 1e-12 * f64)}
 
-    # roofline of the Gram-purity MFMA kernel (FP32 arithmetic), timed per launch with HIP events
+    # roofline of the Gram-purity MFMA kernel, timed per launch with HIP events
     tiled_ms = s32["tiled_ms"]
     roof = None
     if s32["tiled_launches"] > 0 and tiled_ms > 0:
         per_launch_flops = s32["tiled_flops"] / s32["tiled_launches"]
         per_launch_ms = tiled_ms / s32["tiled_launches"]
         achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(),
+        bf = prec == g.SCORE_BF16
+        peak = BF16_PEAK_TFLOPS if bf else FP32_PEAK_TFLOPS
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None if bf else measured_traffic(),
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE, copy-calibrated)",
                 "algorithmic_bytes": s32["tiled_bytes"] / s32["tiled_launches"],
-                "kernel": "k_gram_purity<float, 4>", "launches": int(s32["tiled_launches"]),
-                "avg_ms": per_launch_ms}
+                "kernel": "k_gram_purity_bf16" if bf else "k_gram_purity<float, 4>",
+                "launches": int(s32["tiled_launches"]), "avg_ms": per_launch_ms}
+        if bf:
+            roof["note"] = ("algorithmic flops (4 m^2 k per candidate); the split form issues three BF16 "
+                            "products per real product, so 1/3 of the BF16 peak is its ceiling")
 
     cpu = None
     if not args.no_cpu:
@@ -411,7 +421,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 scoring / c128 commit",
+        "dtype": ("split-bf16 scoring (fp32 accumulate) / c128 commit" if prec == g.SCORE_BF16
+                  else "c64 scoring / c128 commit"),
         "data": "synthetic (seeded brickwork circuits and candidate sets)",
         "config": {"workload": f"qutrit T-doped brickwork d={c.d} n={c.n} layers={len(c.layers)} "
                                f"T={ngates} chi_max={wl.chi_max} cutoff={wl.cutoff} "

@@ -55,7 +55,10 @@ enum {
  * truncation and renormalisation are FP64 in every mode. */
 enum {
   GCAMPS_SCORE_FP64 = 0, /* complex128 scoring */
-  GCAMPS_SCORE_FP32 = 1  /* complex64 scoring, FP64 re-score of the near-tie window */
+  GCAMPS_SCORE_FP32 = 1, /* complex64 scoring, FP64 re-score of the near-tie window */
+  GCAMPS_SCORE_BF16 = 2  /* split-BF16 scoring (each real as hi + lo BF16, FP32 accumulation, relative
+                            error ~2^-16) for matrices above 96 rows, complex64 below; FP64 re-score
+                            of the near-tie window */
 };
 
 typedef struct gcamps_ctx gcamps_ctx;

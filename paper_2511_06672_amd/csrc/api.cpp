@@ -43,8 +43,9 @@ void validate_config(const gcamps_config* c) {
   GC_CHECK(c->n >= 2 && c->n <= kMaxN, GCAMPS_EINVAL, "n out of range [2, 128]");
   GC_CHECK(c->chi_max >= 1 && (size_t)c->chi_max * c->d <= 4096, GCAMPS_EINVAL, "chi_max out of range");
   GC_CHECK(c->cutoff >= 0.0 && c->cutoff < 1.0, GCAMPS_EINVAL, "cutoff out of range [0, 1)");
-  GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->score_prec == GCAMPS_SCORE_FP32, GCAMPS_EINVAL,
-           "score_prec must be GCAMPS_SCORE_FP64 or GCAMPS_SCORE_FP32");
+  GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->score_prec == GCAMPS_SCORE_FP32 ||
+               c->score_prec == GCAMPS_SCORE_BF16,
+           GCAMPS_EINVAL, "score_prec must be GCAMPS_SCORE_FP64, GCAMPS_SCORE_FP32 or GCAMPS_SCORE_BF16");
   GC_CHECK(c->tie_tol >= 0.0, GCAMPS_EINVAL, "tie_tol must be >= 0");
   GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->near_tie >= 1e-6, GCAMPS_EINVAL, "near_tie must be >= 1e-6");
   GC_CHECK(c->max_sweeps >= 0, GCAMPS_EINVAL, "max_sweeps must be >= 0");

@@ -782,7 +782,11 @@ void launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, const z6
 void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu, double* lam, int rel, EigWork& w,
                    DevStatus* st, int* host_sweeps) {
   const double tol = rel ? 1e-14 : 4e-15;
-  const double skip = rel ? 1e-34 : 0.0;
+  // Relative pass: pairs whose diagonal entries are both below 1e-28 lambda_max (lambda_max >=
+  // trace / m) are left alone.  They lie two decades below the rank floor (sigma^2 = 1e-26
+  // sigma_0^2), so no decision depends on them, and exact null directions sit at the rounding
+  // level (~1e-32 of the trace), where a relative criterion cannot be met.
+  const double skip = rel ? 1e-28 / (double)m : 0.0;
   const int max_sweeps = 40;
   if (m <= kSmallEig) {
     hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(256), 0, s, G, ldg, m, U, ldu, lam, rel, tol, skip, max_sweeps,
@@ -830,7 +834,9 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   }
   hipLaunchKernelGGL(k_unpad, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gp, Up, m, mp, U, ldu, lam);
   GC_LAUNCH_CHECK();
-  GC_CHECK(conv, GCAMPS_ENUMERIC, "block Jacobi eigensolver did not converge");
+  GC_CHECK(conv, GCAMPS_ENUMERIC,
+           std::string("block Jacobi eigensolver did not converge (m = ") + std::to_string(m) +
+               (rel ? ", relative-accuracy pass)" : ", first pass)"));
   if (host_sweeps) *host_sweeps = sweeps;
 }
 

@@ -409,6 +409,225 @@ __global__ __launch_bounds__(256) void k_gram_purity(int m, int k, const cx<T>* 
   }
 }
 
+// ------------------------------------------------------------------ split-BF16 scoring
+// Each complex entry x of M_c is held as four BF16 planes: hi = bf16(Re x), lo = bf16(Re x - hi),
+// and the same for Im x, so Re x = hi + lo to about 2^-16 relative.  A product of two such
+// numbers keeps hi*hi + hi*lo + lo*hi (the lo*lo term is below the representation error); the
+// Gram entries then carry a relative error of order 2^-16 and the FP64 window re-score decides.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ bf8 bf8_neg(bf8 x) {
+  return __builtin_bit_cast(bf8, __builtin_bit_cast(us8, x) ^ (unsigned short)0x8000);
+}
+__device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// M_c = reshape(Q_c Theta) (as k_gen_rotated<float>) written as planes [Re hi, Re lo, Im hi, Im lo],
+// each m x k row-major BF16; candidate slot ls at out + ls * stride (stride = 4 m k elements).
+template <int DD>
+__global__ __launch_bounds__(256) void k_gen_rotated_bf16(int d_rt, int chil, int chir, const z64* __restrict__ theta,
+                                                          const c32* __restrict__ qall, const int* __restrict__ list,
+                                                          int c0, int cnt, const int* __restrict__ nlimit,
+                                                          __bf16* __restrict__ out, size_t stride) {
+  const int d = DD > 0 ? DD : d_rt;
+  constexpr int VMAX = DD > 0 ? DD * DD : kMaxD * kMaxD;
+  const int ls = blockIdx.y;
+  const int slot = c0 + ls;
+  if (ls >= cnt || (nlimit && slot >= *nlimit)) return;
+  const int c = list ? list[slot] : slot;
+  const bool rows_first = chil * d <= d * chir;
+  const int k = rows_first ? d * chir : chil * d;
+  const int m = rows_first ? chil * d : d * chir;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)chil * chir) return;
+  int a, b;
+  if (rows_first) {
+    a = (int)(idx / chir);
+    b = (int)(idx % chir);
+  } else {
+    b = (int)(idx / chil);
+    a = (int)(idx % chil);
+  }
+  const int D2 = d * d;
+  const c32* q = qall + (size_t)c * D2 * D2;
+  c32 v[VMAX];
+  const z64* th = theta + (size_t)a * D2 * chir + b;
+#pragma unroll
+  for (int x = 0; x < VMAX; ++x) {
+    if (x >= D2) break;
+    const z64 tv = th[(size_t)x * chir];
+    v[x] = c32{(float)tv.re, (float)tv.im};
+  }
+  __bf16* o = out + (size_t)ls * stride;
+  const size_t plane = (size_t)m * k;
+  for (int y = 0; y < D2; ++y) {
+    const int s1p = y / d, s2p = y - s1p * d;
+    c32 acc = {0.f, 0.f};
+#pragma unroll
+    for (int x = 0; x < VMAX; ++x) {
+      if (x >= D2) break;
+      acc = cadd(acc, cmul(q[y * D2 + x], v[x]));
+    }
+    const size_t row = rows_first ? (size_t)a * d + s1p : (size_t)s2p * chir + b;
+    const size_t col = rows_first ? (size_t)s2p * chir + b : (size_t)a * d + s1p;
+    const size_t e = row * k + col;
+    const __bf16 rh = (__bf16)acc.re, ih = (__bf16)acc.im;
+    o[e] = rh;
+    o[plane + e] = (__bf16)(acc.re - (float)rh);
+    o[2 * plane + e] = ih;
+    o[3 * plane + e] = (__bf16)(acc.im - (float)ih);
+  }
+}
+
+// Purity tiles from the BF16 planes: tile (I, J), I <= J, of rho = M M^H (128 x 128 per
+// workgroup, four waves of 4 x 4 16x16 blocks, v_mfma_f32_16x16x32_bf16).  Per 32-wide
+// k chunk, a lane holds 8 consecutive k of one row per plane: A rows from tile I, B rows from
+// tile J (same layout, rho[r][c] = sum_k M[r][k] conj(M[c][k])):
+//   Re rho += Rh Rh + Rh Rl + Rl Rh + Ih Ih + Ih Il + Il Ih
+//   Im rho += Ih Rh + Ih Rl + Il Rh - Rh Ih - Rh Il - Rl Ih.
+// LDS rows are 64 bytes (4 groups of 8 k); group g of row r sits in slot g ^ ((r >> 2) & 3), so
+// the 16 rows read by a quarter-wave hit disjoint banks.  Two stages, one barrier per chunk,
+// XCD-aware workgroup order as in k_gram_purity.
+constexpr int BT = 128, BKC = 32;
+__global__ __launch_bounds__(256) void k_gram_purity_bf16(int m, int k, const __bf16* __restrict__ nbase,
+                                                          size_t stride, int c0, int cnt,
+                                                          const int* __restrict__ nlimit, int ntp,
+                                                          double* __restrict__ partial) {
+  const int L = blockIdx.x;
+  const int xcd = L & 7, xslot = L >> 3;
+  const int cg = xslot / ntp, tile = xslot - cg * ntp;
+  const int ls = cg * 8 + xcd;
+  const int slot = c0 + ls;
+  if (ls >= cnt || (nlimit && slot >= *nlimit)) return;
+  const __bf16* N = nbase + (size_t)ls * stride;
+  const size_t plane = (size_t)m * k;
+  const int nt = (m + BT - 1) / BT;
+  int I, J;
+  tile_pair(tile, nt, I, J);
+  const bool diag = (I == J);
+  // [stage][panel A/B][plane][row][32 k] as 16-byte groups
+  __shared__ us8 lds[2][2][4][BT][4];
+  __shared__ double red[256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * (BT / 2), wc = (w & 1) * (BT / 2);
+  f4 accr[4][4], acci[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (int q = 0; q < 4; ++q) {
+        accr[i][j][q] = 0.f;
+        acci[i][j][q] = 0.f;
+      }
+  const int r0 = I * BT, q0 = J * BT;
+  const bool kvec = (k % 8) == 0;  // 16-byte aligned groups
+  // per chunk and panel: 4 planes x 128 rows x 4 groups = 2048 groups, 8 per thread
+  us8 pa[8], pb[8];
+  auto fetch_panel = [&](int base_row, int k0, us8* dst) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = t + 256 * u;
+      const int pl = e >> 9, row = (e >> 2) & 127, g = e & 3;
+      const int gr = base_row + row, gk = k0 + 8 * g;
+      us8 v = (us8)(unsigned short)0;
+      if (gr < m) {
+        const __bf16* src = N + pl * plane + (size_t)gr * k + gk;
+        if (kvec && gk + 8 <= k) {
+          v = *reinterpret_cast<const us8*>(src);
+        } else {
+          for (int x = 0; x < 8; ++x)
+            if (gk + x < k) v[x] = __builtin_bit_cast(unsigned short, src[x]);
+        }
+      }
+      dst[u] = v;
+    }
+  };
+  auto stash_panel = [&](int sg, int panel, const us8* src) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = t + 256 * u;
+      const int pl = e >> 9, row = (e >> 2) & 127, g = e & 3;
+      lds[sg][panel][pl][row][g ^ ((row >> 2) & 3)] = src[u];
+    }
+  };
+  fetch_panel(r0, 0, pa);
+  if (!diag) fetch_panel(q0, 0, pb);
+  stash_panel(0, 0, pa);
+  if (!diag) stash_panel(0, 1, pb);
+  __syncthreads();
+  const int bpan = diag ? 0 : 1;
+  const int g = lane >> 4, rr = lane & 15;
+  int sg = 0;
+  for (int k0 = 0; k0 < k; k0 += BKC) {
+    const bool more = k0 + BKC < k;
+    if (more) {
+      fetch_panel(r0, k0 + BKC, pa);
+      if (!diag) fetch_panel(q0, k0 + BKC, pb);
+    }
+    bf8 B[4][4];  // [block j][plane]
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = wc + j * 16 + rr;
+      const int slotg = g ^ ((row >> 2) & 3);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) B[j][pl] = __builtin_bit_cast(bf8, lds[sg][bpan][pl][row][slotg]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wr + i * 16 + rr;
+      const int slotg = g ^ ((row >> 2) & 3);
+      const bf8 rh = __builtin_bit_cast(bf8, lds[sg][0][0][row][slotg]);
+      const bf8 rl = __builtin_bit_cast(bf8, lds[sg][0][1][row][slotg]);
+      const bf8 ih = __builtin_bit_cast(bf8, lds[sg][0][2][row][slotg]);
+      const bf8 il = __builtin_bit_cast(bf8, lds[sg][0][3][row][slotg]);
+      const bf8 nrh = bf8_neg(rh), nrl = bf8_neg(rl);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        f4 re = accr[i][j], im = acci[i][j];
+        re = mfma_bf(rh, B[j][0], re);
+        re = mfma_bf(rh, B[j][1], re);
+        re = mfma_bf(rl, B[j][0], re);
+        re = mfma_bf(ih, B[j][2], re);
+        re = mfma_bf(ih, B[j][3], re);
+        re = mfma_bf(il, B[j][2], re);
+        im = mfma_bf(ih, B[j][0], im);
+        im = mfma_bf(ih, B[j][1], im);
+        im = mfma_bf(il, B[j][0], im);
+        im = mfma_bf(nrh, B[j][2], im);
+        im = mfma_bf(nrh, B[j][3], im);
+        im = mfma_bf(nrl, B[j][2], im);
+        accr[i][j] = re;
+        acci[i][j] = im;
+      }
+    }
+    if (more) {
+      stash_panel(sg ^ 1, 0, pa);
+      if (!diag) stash_panel(sg ^ 1, 1, pb);
+    }
+    __syncthreads();
+    sg ^= 1;
+  }
+  double pur = 0.0, tr = 0.0;
+  const double wgt = diag ? 1.0 : 2.0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (int q = 0; q < 4; ++q) {
+        const int row = r0 + wr + i * 16 + mfma_row_f32(lane, q);
+        const int col = q0 + wc + j * 16 + (lane & 15);
+        if (row < m && col < m) {
+          const double re = (double)accr[i][j][q], im = (double)acci[i][j][q];
+          pur += wgt * (re * re + im * im);
+          if (diag && row == col) tr += re;
+        }
+      }
+  pur = block_sum(pur, red);
+  tr = block_sum(tr, red);
+  if (t == 0) {
+    partial[((size_t)slot * ntp + tile) * 2 + 0] = pur;
+    partial[((size_t)slot * ntp + tile) * 2 + 1] = tr;
+  }
+}
+
 __global__ void k_score_reduce(int ntp, const int* __restrict__ nlimit, int count, const double* __restrict__ partial,
                                double* __restrict__ s2) {
   int slot = blockIdx.x * blockDim.x + threadIdx.x;
@@ -627,6 +846,37 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
     else
       hipLaunchKernelGGL(k_score_small<float>, dim3(count), dim3(SMALL_THREADS), 0, s, d, chil, chir, theta, q64, q32,
                          list, nlimit, s2);
+    GC_LAUNCH_CHECK();
+    return;
+  }
+  if (prec == GCAMPS_SCORE_BF16) {
+    const int nt = (m + BT - 1) / BT;
+    const int ntp = nt * (nt + 1) / 2;
+    GC_CHECK((size_t)count * ntp * 2 <= partial_cap, GCAMPS_ECAPACITY, "scoring partial buffer too small");
+    const size_t stride = 4 * (size_t)m * k;  // BF16 elements per candidate (four planes)
+    const int chunk = (int)std::min<size_t>((size_t)count, nbuf_bytes / (stride * sizeof(__bf16)));
+    GC_CHECK(chunk >= 1, GCAMPS_ECAPACITY, "rotated-matrix buffer too small");
+    __bf16* nb = reinterpret_cast<__bf16*>(nbuf);
+    for (int c0 = 0; c0 < count; c0 += chunk) {
+      const int cnt = std::min(chunk, count - c0);
+      const dim3 gg(blocks_for((size_t)chil * chir, 256), cnt), gp((unsigned)ntp * ((cnt + 7) / 8) * 8);
+      const int ev = (evs && evused && 2 * (*evused) + 1 < evcap) ? 2 * (*evused) : -1;
+      if (d == 3)
+        hipLaunchKernelGGL((k_gen_rotated_bf16<3>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
+                           nlimit, nb, stride);
+      else if (d == 2)
+        hipLaunchKernelGGL((k_gen_rotated_bf16<2>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
+                           nlimit, nb, stride);
+      else
+        hipLaunchKernelGGL((k_gen_rotated_bf16<0>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
+                           nlimit, nb, stride);
+      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
+      hipLaunchKernelGGL(k_gram_purity_bf16, gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp, partial);
+      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
+      GC_LAUNCH_CHECK();
+      if (ev >= 0) ++(*evused);
+    }
+    hipLaunchKernelGGL(k_score_reduce, dim3(blocks_for(count, 128)), dim3(128), 0, s, ntp, nlimit, count, partial, s2);
     GC_LAUNCH_CHECK();
     return;
   }

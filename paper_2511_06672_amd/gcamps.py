@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgcamps.so")
 GCAMPS_OK = 0
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EWORKSPACE", -4: "ECAPACITY",
                 -5: "EDEVICE", -6: "ENUMERIC"}
-SCORE_FP64, SCORE_FP32 = 0, 1
+SCORE_FP64, SCORE_FP32, SCORE_BF16 = 0, 1, 2
 
 SYMBOLS = [
     "gcamps_workspace_bytes", "gcamps_init", "gcamps_destroy", "gcamps_apply_clifford",

@@ -186,6 +186,28 @@ def test_large_matrices_block_paths(g):
     assert aligned_error(st.statevector(), orc.statevector()) < 1e-10
 
 
+def test_bf16_scoring_same_choices(g):
+    """Split-BF16 scoring (matrices above 96 rows) with the FP64 window re-score picks exactly
+    the oracle's disentanglers on saturated bonds (n = 10, bonds up to 243, m up to 243)."""
+    d, n = 3, 10
+    say("split-BF16 scoring on saturated bonds")
+    c = brickwork_circuit(d, n, 12, 12, seed=93)
+    cands = candidate_words(d, 48, 94)
+    st, orc = run_pair(g, c, [], 243, 0.0, prec=2, auto=False, max_candidates=48, near_tie=1e-4)
+    assert max(st.bond_dims()) == 243
+    cs = g.CandSet(d, cands)
+    orc.candidates = list(cands)
+    from oracle.clifford import word_matrix
+    orc._cand_mats = [word_matrix(d, w.gens, w.weyl) for w in cands]
+    st.disentangle(cs)
+    orc.disentangle()
+    assert st.stats()["tiled_launches"] > 0          # the BF16 Gram kernel ran
+    assert np.array_equal(st.choice_log(), oracle_log(orc))
+    assert np.array_equal(st.tableau(), orc.tab.export())
+    assert st.bond_dims() == orc.mps.bond_dims()
+    assert aligned_error(st.statevector(), orc.statevector()) < 1e-10
+
+
 def test_error_paths(g):
     say("error paths")
     st = g.State(g.make_config(3, 4, 9, 0.0))
