@@ -331,6 +331,7 @@ def main():
     ap.add_argument("--serial-check", action="store_true", help="batch: also run on one lane")
     ap.add_argument("--score", choices=["fp32", "bf16"], default="fp32",
                     help="headline: precision of the timed path's candidate scoring")
+    ap.add_argument("--no-bf16", action="store_true", help="headline: skip the split-BF16 comparison run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -386,6 +387,18 @@ def main():
                  "fidelity_rel_diff": abs(f32 - f64) / f64,
                  "equal_final_fidelity": bool(same_choices and abs(f32 - f64) <= 1e-12 * f64)}
 
+    resbf = None
+    if not args.no_bf16 and prec != g.SCORE_BF16:
+        log("split-BF16-scored path (same workload)")
+        stb, tb = run_circuit(g, wl, g.SCORE_BF16)
+        sb = stb.stats()
+        resbf = {"value": ngates / tb, "ms_per_step": 1e3 * tb, "fidelity": stb.fidelity(),
+                 "choices_identical_to_timed_path": bool(np.array_equal(stb.choice_log(), st32.choice_log())),
+                 "gram_kernel": "k_gram_purity_bf16",
+                 "gram_tflops_algorithmic": (sb["tiled_flops"] / (sb["tiled_ms"] * 1e-3) / 1e12
+                                             if sb["tiled_ms"] > 0 else None),
+                 "rescored_candidates": int(sb["rescored"])}
+
     # roofline of the Gram-purity MFMA kernel, timed per launch with HIP events
     tiled_ms = s32["tiled_ms"]
     roof = None
@@ -432,6 +445,7 @@ def main():
         "final_bond_dim_max": int(max(st32.bond_dims())),
         "fp64_path": res64,
         "speedup_vs_fp64": (res64["ms_per_step"] / (1e3 * t32)) if res64 else None,
+        "bf16_path": resbf,
         "rescored_candidates": int(s32["rescored"]),
         "roofline": roof,
         "cpu_baseline": cpu,

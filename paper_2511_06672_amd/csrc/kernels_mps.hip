@@ -564,7 +564,7 @@ __global__ __launch_bounds__(256) void k_gram_purity_bf16(int m, int k, const __
       fetch_panel(r0, k0 + BKC, pa);
       if (!diag) fetch_panel(q0, k0 + BKC, pb);
     }
-    bf8 B[4][4];  // [block j][plane]
+    bf8 A[4][6], B[4][4];  // A: [block i][Rh, Rl, Ih, Il, -Rh, -Rl]; B: [block j][Rh, Rl, Ih, Il]
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = wc + j * 16 + rr;
@@ -576,29 +576,25 @@ __global__ __launch_bounds__(256) void k_gram_purity_bf16(int m, int k, const __
     for (int i = 0; i < 4; ++i) {
       const int row = wr + i * 16 + rr;
       const int slotg = g ^ ((row >> 2) & 3);
-      const bf8 rh = __builtin_bit_cast(bf8, lds[sg][0][0][row][slotg]);
-      const bf8 rl = __builtin_bit_cast(bf8, lds[sg][0][1][row][slotg]);
-      const bf8 ih = __builtin_bit_cast(bf8, lds[sg][0][2][row][slotg]);
-      const bf8 il = __builtin_bit_cast(bf8, lds[sg][0][3][row][slotg]);
-      const bf8 nrh = bf8_neg(rh), nrl = bf8_neg(rl);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        f4 re = accr[i][j], im = acci[i][j];
-        re = mfma_bf(rh, B[j][0], re);
-        re = mfma_bf(rh, B[j][1], re);
-        re = mfma_bf(rl, B[j][0], re);
-        re = mfma_bf(ih, B[j][2], re);
-        re = mfma_bf(ih, B[j][3], re);
-        re = mfma_bf(il, B[j][2], re);
-        im = mfma_bf(ih, B[j][0], im);
-        im = mfma_bf(ih, B[j][1], im);
-        im = mfma_bf(il, B[j][0], im);
-        im = mfma_bf(nrh, B[j][2], im);
-        im = mfma_bf(nrh, B[j][3], im);
-        im = mfma_bf(nrl, B[j][2], im);
-        accr[i][j] = re;
-        acci[i][j] = im;
-      }
+      for (int pl = 0; pl < 4; ++pl) A[i][pl] = __builtin_bit_cast(bf8, lds[sg][0][pl][row][slotg]);
+      A[i][4] = bf8_neg(A[i][0]);
+      A[i][5] = bf8_neg(A[i][1]);
+    }
+    // term-major order: consecutive MFMAs write different accumulators
+    constexpr int TA[12] = {0, 0, 1, 2, 2, 3, 2, 2, 3, 4, 4, 5};
+    constexpr int TB[12] = {0, 1, 0, 2, 3, 2, 0, 1, 0, 2, 3, 2};
+#pragma unroll
+    for (int term = 0; term < 12; ++term) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (term < 6)
+            accr[i][j] = mfma_bf(A[i][TA[term]], B[j][TB[term]], accr[i][j]);
+          else
+            acci[i][j] = mfma_bf(A[i][TA[term]], B[j][TB[term]], acci[i][j]);
+        }
     }
     if (more) {
       stash_panel(sg ^ 1, 0, pa);
