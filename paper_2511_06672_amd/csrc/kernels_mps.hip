@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_gen_rotated(int d_rt, int chil, int chi
 // of BL x BL 16x16 blocks (TT = 32 * BL).  The epilogue writes sum |rho_tile|^2 (doubled off the
 // diagonal) and the tile's trace to partial[slot][tile].
 template <typename T, int BL>
-__global__ __launch_bounds__(256) void k_gram_purity(int m, int k, const cx<T>* __restrict__ nbase, size_t stride,
+__global__ __launch_bounds__(256, 2) void k_gram_purity(int m, int k, const cx<T>* __restrict__ nbase, size_t stride,
                                                      int c0, int cnt, const int* __restrict__ nlimit, int ntp,
                                                      double* __restrict__ partial) {
   typedef typename AccT<T>::type acc_t;
