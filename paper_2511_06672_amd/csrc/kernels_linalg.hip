@@ -200,86 +200,98 @@ __device__ __forceinline__ bool rot_params(double a, double b, double gr, double
 
 // A sequence of parallel Jacobi steps on the Hermitian H (2*half indices, half <= 16) held as
 // two re/im plane pairs in LDS (double buffer).  Step s uses the pairs tab[s][k] = (p, q).
-// Thread (k1, k2) (k1, k2 < half) owns the 2x2 block of rows (p_k1, q_k1) and columns
-// (p_k2, q_k2): it computes the rotations of pairs k1 and k2 from the old buffer, writes its
-// rotated block into the new buffer, and applies rotation k1 to rows 2 k2 and 2 k2 + 1 of the
-// eigenvector accumulator (V planes, in place; 2 * half rows in total), so a step needs one
-// barrier and every rotation is computed once per thread that uses it.  Returns the index
-// (0/1) of the buffer holding the result; *any is set when a rotation happened.
+// Item (k1, k2) (k1, k2 < half) is the 2x2 block of rows (p_k1, q_k1) and columns
+// (p_k2, q_k2): it needs rotations k1 and k2, computed from the old buffer, and its rotated block
+// goes to the new buffer.  Rotation k1 is also applied to rows 2 k2 and 2 k2 + 1 of the
+// eigenvector accumulator (V planes, in place; 2 * half rows in total).  With at least
+// 2 half^2 threads the block update and the V update of an item run on different threads
+// (each computes the rotations it needs), otherwise one thread does both; items are dealt
+// round-robin.  One barrier per step.  Returns the index (0/1) of the buffer holding the result;
+// *any is set when a rotation happened.
 __device__ int jacobi_steps(double* __restrict__ h0r, double* __restrict__ h0i, double* __restrict__ h1r,
                             double* __restrict__ h1i, int ldh, int half, const unsigned char* __restrict__ tab,
                             int nsteps, double* __restrict__ vr, double* __restrict__ vi, int ldv,
                             const JacobiArgs& ja, int* any) {
-  const int t = threadIdx.x;
-  const bool active = t < half * half;
-  const int k1 = active ? (int)(((float)t + 0.5f) / (float)half) : 0;
-  const int k2 = t - k1 * half;
-  const int v0 = 2 * k2, v1 = 2 * k2 + 1;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int nitems = half * half;
+  const bool split = nt >= 2 * nitems;
+  const int nwork = split ? 2 * nitems : nitems;
   int cur = 0;
   for (int step = 0; step < nsteps; ++step) {
-    if (active) {
-      const unsigned char* pt = tab + step * 2 * half;
-      const double* __restrict__ ir = cur ? h1r : h0r;
-      const double* __restrict__ ii = cur ? h1i : h0i;
-      double* __restrict__ orr = cur ? h0r : h1r;
-      double* __restrict__ oi = cur ? h0i : h1i;
-      const int p1 = pt[2 * k1], q1 = pt[2 * k1 + 1], p2 = pt[2 * k2], q2 = pt[2 * k2 + 1];
+    const unsigned char* pt = tab + step * 2 * half;
+    const double* __restrict__ ir = cur ? h1r : h0r;
+    const double* __restrict__ ii = cur ? h1i : h0i;
+    double* __restrict__ orr = cur ? h0r : h1r;
+    double* __restrict__ oi = cur ? h0i : h1i;
+    for (int e0 = t; e0 < nwork; e0 += nt) {
+      const bool do_v = !split || e0 >= nitems;
+      const bool do_h = !split || e0 < nitems;
+      const int e = (split && e0 >= nitems) ? e0 - nitems : e0;
+      const int k1 = (int)(((float)e + 0.5f) / (float)half);
+      const int k2 = e - k1 * half;
+      const int p1 = pt[2 * k1], q1 = pt[2 * k1 + 1];
       const double a1 = ir[p1 * ldh + p1], b1 = ir[q1 * ldh + q1], g1r = ir[p1 * ldh + q1], g1i = ii[p1 * ldh + q1];
-      const double a2 = ir[p2 * ldh + p2], b2 = ir[q2 * ldh + q2], g2r = ir[p2 * ldh + q2], g2i = ii[p2 * ldh + q2];
-      double ar = ir[p1 * ldh + p2], ai = ii[p1 * ldh + p2];
-      double br = ir[p1 * ldh + q2], bi = ii[p1 * ldh + q2];
-      double cr = ir[q1 * ldh + p2], ci = ii[q1 * ldh + p2];
-      double dr = ir[q1 * ldh + q2], di = ii[q1 * ldh + q2];
-      const double w0pr = vr[v0 * ldv + p1], w0pi = vi[v0 * ldv + p1];
-      const double w0qr = vr[v0 * ldv + q1], w0qi = vi[v0 * ldv + q1];
-      const double w1pr = vr[v1 * ldv + p1], w1pi = vi[v1 * ldv + p1];
-      const double w1qr = vr[v1 * ldv + q1], w1qi = vi[v1 * ldv + q1];
-      double c1, sp1r, sp1i, na1, nb1, c2, sp2r, sp2i, na2, nb2;
+      double c1, sp1r, sp1i, na1, nb1;
       const bool f1 = rot_params(a1, b1, g1r, g1i, ja, c1, sp1r, sp1i, na1, nb1);
-      const bool f2 = rot_params(a2, b2, g2r, g2i, ja, c2, sp2r, sp2i, na2, nb2);
-      if (f1) {  // rows: r_p' = c r_p - sp r_q ; r_q' = conj(sp) r_p + c r_q
-        const double nar = c1 * ar - (sp1r * cr - sp1i * ci), nai = c1 * ai - (sp1r * ci + sp1i * cr);
-        const double nbr = c1 * br - (sp1r * dr - sp1i * di), nbi = c1 * bi - (sp1r * di + sp1i * dr);
-        const double ncr = c1 * cr + (sp1r * ar + sp1i * ai), nci = c1 * ci + (sp1r * ai - sp1i * ar);
-        const double ndr = c1 * dr + (sp1r * br + sp1i * bi), ndi = c1 * di + (sp1r * bi - sp1i * br);
-        ar = nar;
-        ai = nai;
-        br = nbr;
-        bi = nbi;
-        cr = ncr;
-        ci = nci;
-        dr = ndr;
-        di = ndi;
+      if (do_h) {
+        const int p2 = pt[2 * k2], q2 = pt[2 * k2 + 1];
+        const double a2 = ir[p2 * ldh + p2], b2 = ir[q2 * ldh + q2], g2r = ir[p2 * ldh + q2],
+                     g2i = ii[p2 * ldh + q2];
+        double ar = ir[p1 * ldh + p2], ai = ii[p1 * ldh + p2];
+        double br = ir[p1 * ldh + q2], bi = ii[p1 * ldh + q2];
+        double cr = ir[q1 * ldh + p2], ci = ii[q1 * ldh + p2];
+        double dr = ir[q1 * ldh + q2], di = ii[q1 * ldh + q2];
+        double c2, sp2r, sp2i, na2, nb2;
+        const bool f2 = rot_params(a2, b2, g2r, g2i, ja, c2, sp2r, sp2i, na2, nb2);
+        if (f1) {  // rows: r_p' = c r_p - sp r_q ; r_q' = conj(sp) r_p + c r_q
+          const double nar = c1 * ar - (sp1r * cr - sp1i * ci), nai = c1 * ai - (sp1r * ci + sp1i * cr);
+          const double nbr = c1 * br - (sp1r * dr - sp1i * di), nbi = c1 * bi - (sp1r * di + sp1i * dr);
+          const double ncr = c1 * cr + (sp1r * ar + sp1i * ai), nci = c1 * ci + (sp1r * ai - sp1i * ar);
+          const double ndr = c1 * dr + (sp1r * br + sp1i * bi), ndi = c1 * di + (sp1r * bi - sp1i * br);
+          ar = nar;
+          ai = nai;
+          br = nbr;
+          bi = nbi;
+          cr = ncr;
+          ci = nci;
+          dr = ndr;
+          di = ndi;
+        }
+        if (f2) {  // cols: c_p' = c c_p - conj(sp) c_q ; c_q' = sp c_p + c c_q
+          const double nar = c2 * ar - (sp2r * br + sp2i * bi), nai = c2 * ai - (sp2r * bi - sp2i * br);
+          const double ncr = c2 * cr - (sp2r * dr + sp2i * di), nci = c2 * ci - (sp2r * di - sp2i * dr);
+          const double nbr = c2 * br + (sp2r * ar - sp2i * ai), nbi = c2 * bi + (sp2r * ai + sp2i * ar);
+          const double ndr = c2 * dr + (sp2r * cr - sp2i * ci), ndi = c2 * di + (sp2r * ci + sp2i * cr);
+          ar = nar;
+          ai = nai;
+          br = nbr;
+          bi = nbi;
+          cr = ncr;
+          ci = nci;
+          dr = ndr;
+          di = ndi;
+        }
+        if (k1 == k2 && f1) {
+          ar = na1;
+          dr = nb1;
+          ai = di = br = bi = cr = ci = 0.0;
+        }
+        if (f1 || f2) *any = 1;
+        orr[p1 * ldh + p2] = ar;
+        oi[p1 * ldh + p2] = ai;
+        orr[p1 * ldh + q2] = br;
+        oi[p1 * ldh + q2] = bi;
+        orr[q1 * ldh + p2] = cr;
+        oi[q1 * ldh + p2] = ci;
+        orr[q1 * ldh + q2] = dr;
+        oi[q1 * ldh + q2] = di;
       }
-      if (f2) {  // cols: c_p' = c c_p - conj(sp) c_q ; c_q' = sp c_p + c c_q
-        const double nar = c2 * ar - (sp2r * br + sp2i * bi), nai = c2 * ai - (sp2r * bi - sp2i * br);
-        const double ncr = c2 * cr - (sp2r * dr + sp2i * di), nci = c2 * ci - (sp2r * di - sp2i * dr);
-        const double nbr = c2 * br + (sp2r * ar - sp2i * ai), nbi = c2 * bi + (sp2r * ai + sp2i * ar);
-        const double ndr = c2 * dr + (sp2r * cr - sp2i * ci), ndi = c2 * di + (sp2r * ci + sp2i * cr);
-        ar = nar;
-        ai = nai;
-        br = nbr;
-        bi = nbi;
-        cr = ncr;
-        ci = nci;
-        dr = ndr;
-        di = ndi;
-      }
-      if (k1 == k2 && f1) {
-        ar = na1;
-        dr = nb1;
-        ai = di = br = bi = cr = ci = 0.0;
-      }
-      if (f1 || f2) *any = 1;
-      orr[p1 * ldh + p2] = ar;
-      oi[p1 * ldh + p2] = ai;
-      orr[p1 * ldh + q2] = br;
-      oi[p1 * ldh + q2] = bi;
-      orr[q1 * ldh + p2] = cr;
-      oi[q1 * ldh + p2] = ci;
-      orr[q1 * ldh + q2] = dr;
-      oi[q1 * ldh + q2] = di;
-      if (f1) {  // V columns (p1, q1), rows v0, v1: v_p' = c v_p - conj(sp) v_q ; v_q' = sp v_p + c v_q
+      if (do_v && f1) {  // V columns (p1, q1), rows v0, v1: v_p' = c v_p - conj(sp) v_q ; v_q' = sp v_p + c v_q
+        const int v0 = 2 * k2, v1 = 2 * k2 + 1;
+        const double w0pr = vr[v0 * ldv + p1], w0pi = vi[v0 * ldv + p1];
+        const double w0qr = vr[v0 * ldv + q1], w0qi = vi[v0 * ldv + q1];
+        const double w1pr = vr[v1 * ldv + p1], w1pi = vi[v1 * ldv + p1];
+        const double w1qr = vr[v1 * ldv + q1], w1qi = vi[v1 * ldv + q1];
         vr[v0 * ldv + p1] = c1 * w0pr - (sp1r * w0qr + sp1i * w0qi);
         vi[v0 * ldv + p1] = c1 * w0pi - (sp1r * w0qi - sp1i * w0qr);
         vr[v0 * ldv + q1] = c1 * w0qr + (sp1r * w0pr - sp1i * w0pi);
@@ -369,6 +381,7 @@ __global__ __launch_bounds__(256) void k_jacobi_small(const z64* __restrict__ G,
 
 // ----------------------------------------------------------------------- block Jacobi
 constexpr int BJ = kBlk;      // block size (16)
+constexpr int kSolveThreads = 512;  // threads per 32x32 sub-problem (block and V updates split)
 constexpr int BJ2 = 2 * kBlk; // pair size (32)
 constexpr int SLD = BJ2 + 1;  // LDS leading dimension (plane layout)
 
@@ -377,7 +390,7 @@ constexpr int SLD = BJ2 + 1;  // LDS leading dimension (plane layout)
 // outer sweep runs a full round-robin sweep over the 32 indices (covering the pairs inside each
 // block); later steps rotate only the 16 x 16 inter-block pairs.  Over one outer sweep every
 // index pair is visited once.
-__global__ __launch_bounds__(256) void k_jblock_solve(const z64* __restrict__ Gp, int mp, int nb, int step, double thr,
+__global__ __launch_bounds__(512) void k_jblock_solve(const z64* __restrict__ Gp, int mp, int nb, int step, double thr,
                                                       double tol, double skip, int rel, z64* __restrict__ Vout,
                                                       int* __restrict__ pair_flag, int* __restrict__ any_flag) {
   constexpr int PL = BJ2 * SLD;
@@ -816,7 +829,7 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   for (int sw = 0; sw < max_sweeps; ++sw) {
     GC_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
     for (int step = 0; step < nb - 1; ++step) {
-      hipLaunchKernelGGL(k_jblock_solve, dim3(half), dim3(256), 0, s, Gp, mp, nb, step, thr, tol, skipv, rel, w.V,
+      hipLaunchKernelGGL(k_jblock_solve, dim3(half), dim3(kSolveThreads), 0, s, Gp, mp, nb, step, thr, tol, skipv, rel, w.V,
                          w.flags + 1, w.flags);
       GC_LAUNCH_CHECK();
       int tiles = half * (half + 1) / 2 + (mp / BJ2) * half;
