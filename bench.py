@@ -13,6 +13,11 @@ both must give identical choice logs and fidelity estimates.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu]
 
+Beside the timed path the headline line carries the same circuit with split-BF16 scoring
+(`bf16_path`) and with replica-tensor scoring (`replica_path`: FP64 scores of all candidates
+from one Gram product of Theta per bond, an exact rewriting of the purity), each with its
+rate and whether its choice log equals the timed path's.
+
 A second workload measures batching of independent circuits (qutrits, circuit i with
 n_i ~ U{8..48} sites, T_i ~ U{4..60} T gates at uniform positions, 2 n_i layers,
 chi_max = 128, cutoff 1e-10, 512 shared candidates, FP32-scored) on concurrent lanes:
@@ -47,6 +52,9 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 NEAR_TIE = 1e-4
+
+
+PREC_NAMES = {0: "fp64", 1: "fp32", 2: "bf16", 3: "replica"}
 
 
 def log(msg):
@@ -93,7 +101,7 @@ def run_circuit(g, wl, prec, progress=True):
             st.apply_phase_rotation(ph.site, ph.phi)
             gi += 1
             if progress and gi % 5 == 0:
-                log(f"  [{'fp32' if prec else 'fp64'}] gate {gi}/{c.n_phase_gates} "
+                log(f"  [{PREC_NAMES[prec]}] gate {gi}/{c.n_phase_gates} "
                     f"maxchi {max(st.bond_dims())} t={time.perf_counter() - t0:.1f}s")
     torch.cuda.synchronize()
     return st, time.perf_counter() - t0
@@ -332,6 +340,8 @@ def main():
     ap.add_argument("--score", choices=["fp32", "bf16"], default="fp32",
                     help="headline: precision of the timed path's candidate scoring")
     ap.add_argument("--no-bf16", action="store_true", help="headline: skip the split-BF16 comparison run")
+    ap.add_argument("--no-replica", action="store_true",
+                    help="headline: skip the replica-tensor-scored comparison run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -399,6 +409,17 @@ def main():
                                              if sb["tiled_ms"] > 0 else None),
                  "rescored_candidates": int(sb["rescored"])}
 
+    resrep = None
+    if not args.no_replica:
+        log("replica-tensor-scored path (same workload)")
+        str_, trep = run_circuit(g, wl, g.SCORE_REPLICA)
+        sr = str_.stats()
+        resrep = {"value": ngates / trep, "ms_per_step": 1e3 * trep, "fidelity": str_.fidelity(),
+                  "choices_identical_to_timed_path": bool(np.array_equal(str_.choice_log(), st32.choice_log())),
+                  "full_set_scoring_ms": sr["score_ms"], "timed_path_full_set_scoring_ms": s32["score_ms"],
+                  "scoring_gflop": sr["score_flops"] / 1e9,
+                  "rescored_candidates": int(sr["rescored"])}
+
     # roofline of the Gram-purity MFMA kernel, timed per launch with HIP events
     tiled_ms = s32["tiled_ms"]
     roof = None
@@ -446,6 +467,7 @@ def main():
         "fp64_path": res64,
         "speedup_vs_fp64": (res64["ms_per_step"] / (1e3 * t32)) if res64 else None,
         "bf16_path": resbf,
+        "replica_path": resrep,
         "rescored_candidates": int(s32["rescored"]),
         "roofline": roof,
         "cpu_baseline": cpu,

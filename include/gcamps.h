@@ -56,9 +56,16 @@ enum {
 enum {
   GCAMPS_SCORE_FP64 = 0, /* complex128 scoring */
   GCAMPS_SCORE_FP32 = 1, /* complex64 scoring, FP64 re-score of the near-tie window */
-  GCAMPS_SCORE_BF16 = 2  /* split-BF16 scoring (each real as hi + lo BF16, FP32 accumulation, relative
+  GCAMPS_SCORE_BF16 = 2, /* split-BF16 scoring (each real as hi + lo BF16, FP32 accumulation, relative
                             error ~2^-16) for matrices above 96 rows, complex64 below; FP64 re-score
                             of the near-tie window */
+  GCAMPS_SCORE_REPLICA = 3 /* FP64 replica-tensor scoring (d = 2, 3 only): the purity of Q_c Theta (§3)
+                              rewritten as sum W(Theta) o V_c, W from the Gram of Theta over its
+                              larger bond and V_c a table built once per candidate set, so a bond
+                              costs one Gram product plus one d^8 dot product per candidate (exact
+                              up to rounding; not a step of the paper).  Matrices of at most 96
+                              rows are scored directly in FP64.  The FP64 re-score of the near-tie
+                              window then decides, as in the FP32 mode. */
 };
 
 typedef struct gcamps_ctx gcamps_ctx;
@@ -144,6 +151,15 @@ int32_t gcamps_set_candset(gcamps_ctx* ctx, const gcamps_candset* set);
  * everywhere or after max_sweeps.  set may be NULL to use the attached set.
  * out_sweeps / out_changed_bonds may be NULL.
  * Errors: EINVAL, ECAPACITY, ENUMERIC, EDEVICE. */
+/* S2 of every candidate of the attached set at bond (bond, bond + 1) of the current state, the
+ * disentangler's full-set score (§3; the Rényi-2 entropy of the rotated two-site tensor is how
+ * this library reads the paper's entanglement measure) in the ctx's scoring mode (FP32/BF16: the low-precision first
+ * pass).  Moves the orthogonality centre to `bond` (exact moves; the state is unchanged up to
+ * rounding and numerically zero directions) and commits nothing.  out: host array of cap >=
+ * candidate count doubles.  Errors: EINVAL (bond outside [0, n-2], no candidate set, cap too
+ * small), EDEVICE. */
+int32_t gcamps_score_bond(gcamps_ctx* ctx, int32_t bond, double* out, int64_t cap);
+
 int32_t gcamps_disentangle(gcamps_ctx* ctx, const gcamps_candset* set, int32_t* out_sweeps,
                            int32_t* out_changed_bonds);
 
@@ -182,7 +198,8 @@ int32_t gcamps_get_choice_log(gcamps_ctx* ctx, int32_t* out, int64_t cap, int64_
 int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap, int32_t dims[3]);
 /* Statistics (16 doubles): [0] non-Clifford gates applied, [1] bonds scored,
  * [2] candidates re-scored in FP64 (FP32 mode), [3] degenerate cuts flagged,
- * [4] algorithmic flops of full-set scoring, [5] algorithmic flops of the Gram products of
+ * [4] algorithmic flops of full-set scoring (direct: N_c (4 m^2 k + 8 d^4 chi_l chi_r) per bond;
+ * replica mode: 4 (X d^2)^2 Y + 8 X (X + 1) / 2 d^8 + 2 N_c d^8 with X, Y the smaller and larger bond), [5] algorithmic flops of the Gram products of
  * the factorisations, [6] full-set scoring kernel time in ms (device events), [7] total time
  * inside gcamps_* calls in ms (host clock), [8] flops of the FP64 window re-score, [9] its
  * kernel time in ms, [10] scoring calls (bonds x passes), [11] launches of the Gram-purity MFMA

@@ -33,7 +33,6 @@ bool is_prime(int d) {
   return true;
 }
 
-inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 
 void validate_config(const gcamps_config* c) {
@@ -44,8 +43,10 @@ void validate_config(const gcamps_config* c) {
   GC_CHECK(c->chi_max >= 1 && (size_t)c->chi_max * c->d <= 4096, GCAMPS_EINVAL, "chi_max out of range");
   GC_CHECK(c->cutoff >= 0.0 && c->cutoff < 1.0, GCAMPS_EINVAL, "cutoff out of range [0, 1)");
   GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->score_prec == GCAMPS_SCORE_FP32 ||
-               c->score_prec == GCAMPS_SCORE_BF16,
-           GCAMPS_EINVAL, "score_prec must be GCAMPS_SCORE_FP64, GCAMPS_SCORE_FP32 or GCAMPS_SCORE_BF16");
+               c->score_prec == GCAMPS_SCORE_BF16 || c->score_prec == GCAMPS_SCORE_REPLICA,
+           GCAMPS_EINVAL, "score_prec must be GCAMPS_SCORE_FP64, _FP32, _BF16 or _REPLICA");
+  GC_CHECK(c->score_prec != GCAMPS_SCORE_REPLICA || c->d <= 3, GCAMPS_EUNSUPPORTED,
+           "replica scoring is implemented for d = 2 and 3");
   GC_CHECK(c->tie_tol >= 0.0, GCAMPS_EINVAL, "tie_tol must be >= 0");
   GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->near_tie >= 1e-6, GCAMPS_EINVAL, "near_tie must be >= 1e-6");
   GC_CHECK(c->max_sweeps >= 0, GCAMPS_EINVAL, "max_sweeps must be >= 0");
@@ -125,7 +126,12 @@ Layout make_layout(const gcamps_config& c) {
   L.off_partial = take(L.ncand * L.ntp * 2 * sizeof(double));
   // rotated candidate matrices of the tiled scorer: up to 64 candidates of m x k complex128
   L.nbuf_bytes = (size_t)std::min<size_t>(64, L.ncand) * L.theta_elems * sizeof(z64);
+  // replica scoring keeps its scratch (Gram of Theta, partial sums) in the same buffer: the
+  // first pass is done before the window re-score writes rotated matrices there
+  const bool replica = c.score_prec == GCAMPS_SCORE_REPLICA;
+  if (replica) L.nbuf_bytes = std::max(L.nbuf_bytes, replica_scratch_bytes(c.d, c.chi_max));
   L.off_nbuf = take(L.nbuf_bytes);
+  L.off_rtab = take(replica ? replica_table_elems(c.d, (int)L.ncand) * sizeof(z64) : 0);
   const size_t D4 = d * d * d * d;
   L.off_q64 = take(L.ncand * D4 * sizeof(z64));
   L.off_q32 = take(L.ncand * D4 * sizeof(c32));
@@ -206,6 +212,7 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
     c->partial = reinterpret_cast<double*>(w + lay.off_partial);
     c->nbuf = w + lay.off_nbuf;
     c->q64 = reinterpret_cast<z64*>(w + lay.off_q64);
+    c->rtab = cfg->score_prec == GCAMPS_SCORE_REPLICA ? reinterpret_cast<z64*>(w + lay.off_rtab) : nullptr;
     c->q32 = reinterpret_cast<c32*>(w + lay.off_q32);
     c->qinv = reinterpret_cast<uint32_t*>(w + lay.off_qinv);
     int* tab = reinterpret_cast<int*>(w + lay.off_tab);
@@ -330,6 +337,7 @@ static void upload_candset(gcamps_ctx* ctx, const gcamps_candset* set) {
   GC_HIP(hipMemcpyAsync(ctx->q64, q64.data(), q64.size() * sizeof(z64), hipMemcpyHostToDevice, ctx->stream));
   GC_HIP(hipMemcpyAsync(ctx->q32, q32.data(), q32.size() * sizeof(c32), hipMemcpyHostToDevice, ctx->stream));
   GC_HIP(hipMemcpyAsync(ctx->qinv, inv.data(), inv.size() * sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream));
+  if (ctx->rtab) launch_replica_tables(ctx->stream, d, set->count, ctx->q64, ctx->rtab);
   GC_HIP(hipStreamSynchronize(ctx->stream));
   ctx->ncand = set->count;
   ctx->cand_uid = set->uid;
@@ -339,6 +347,16 @@ int32_t gcamps_set_candset(gcamps_ctx* ctx, const gcamps_candset* set) {
   return guarded(ctx, [&] {
     GC_CHECK(ctx && set, GCAMPS_EINVAL, "null argument");
     upload_candset(ctx, set);
+  });
+}
+
+int32_t gcamps_score_bond(gcamps_ctx* ctx, int32_t bond, double* out, int64_t cap) {
+  return guarded(ctx, [&] {
+    GC_CHECK(ctx && out, GCAMPS_EINVAL, "null argument");
+    GC_CHECK(bond >= 0 && bond < ctx->n - 1, GCAMPS_EINVAL, "bond outside [0, n-2]");
+    GC_CHECK(ctx->ncand >= 1, GCAMPS_EINVAL, "no candidate set attached");
+    GC_CHECK(cap >= ctx->ncand, GCAMPS_EINVAL, "output capacity below the candidate count");
+    ctx->score_bond(bond, out);
   });
 }
 

@@ -20,7 +20,7 @@ struct Layout {
   int nslots;
   size_t off_slots, off_theta, off_G, off_U, off_Z, off_Utmp, off_B, off_B2, off_sig2, off_sig, off_lam,
       off_perm, off_eigG, off_eigV, off_flags, off_s2, off_s2w, off_wlist, off_partial, off_nbuf, nbuf_bytes, off_q64, off_q32,
-      off_qinv, off_tab, off_target, off_weyl, off_err, off_status, off_luts, off_sites, total;
+      off_rtab, off_qinv, off_tab, off_target, off_weyl, off_err, off_status, off_luts, off_sites, total;
 };
 
 Layout make_layout(const gcamps_config& c);
@@ -102,6 +102,7 @@ struct gcamps_ctx {
   int *perm = nullptr, *wlist = nullptr;
   z64* q64 = nullptr;
   c32* q32 = nullptr;
+  z64* rtab = nullptr;  // replica-scoring tables of the candidate set (replica mode only)
   uint32_t* qinv = nullptr;
   EigWork eig{};
   // MPS
@@ -388,6 +389,19 @@ struct gcamps_ctx {
     stats[0] += 1;
   }
 
+  // Full-set scores of bond (i, i+1) in the configured mode, to host memory; commits nothing.
+  void score_bond(int i, double* out) {
+    move_centre(i);
+    const int cl = chi[i], cm = chi[i + 1], cr = chi[i + 2];
+    launch_zgemm(stream, 0, 0, cl * d, d * cr, cm, site[i], cm, site[i + 1], d * cr, theta, d * cr, z64{1.0, 0.0},
+                 0, 0);
+    const size_t pcap = lay.ncand * lay.ntp * 2;
+    launch_score(stream, cfg.score_prec, d, cl, cr, theta, q64, q32, nullptr, ncand, nullptr, s2, partial, pcap, nbuf,
+                 lay.nbuf_bytes, nullptr, 0, nullptr, rtab);
+    GC_HIP(hipMemcpyAsync(out, s2, (size_t)ncand * sizeof(double), hipMemcpyDeviceToHost, stream));
+    GC_HIP(hipStreamSynchronize(stream));
+  }
+
   void disentangle(int* out_sweeps, int* out_changed) {
     GC_CHECK(ncand >= 1, GCAMPS_EINVAL, "no candidate set attached");
     int sweeps = 0, changed_total = 0;
@@ -425,7 +439,7 @@ struct gcamps_ctx {
           const double pflops = 4.0 * mm * mm * kk + 8.0 * std::pow((double)d, 4) * cl * cr;
           GC_HIP(hipEventRecord(ev0, stream));
           launch_score(stream, prec, d, cl, cr, theta, q64, q32, nullptr, ncand, nullptr, s2, partial, pcap, nbuf,
-                       lay.nbuf_bytes, gram_ev.data(), (int)gram_ev.size(), &gram_used);
+                       lay.nbuf_bytes, gram_ev.data(), (int)gram_ev.size(), &gram_used, rtab);
           GC_HIP(hipEventRecord(ev1, stream));
           if (prec == GCAMPS_SCORE_FP64) {
             launch_select(stream, ncand, s2, cfg.tie_tol, st);
@@ -437,7 +451,13 @@ struct gcamps_ctx {
             GC_HIP(hipEventRecord(ev3, stream));
             launch_select_window(stream, wlist, s2w, cfg.tie_tol, st);
           }
-          stats[4] += (double)ncand * pflops;
+          if (prec == GCAMPS_SCORE_REPLICA && mm > kScoreSmallM) {
+            // Gram of Theta over the larger bond (Hermitian half), pair sum, one d^8 dot per candidate
+            const double X = std::min(cl, cr), Y = std::max(cl, cr), XD = X * d * d, R2 = std::pow((double)d, 8);
+            stats[4] += 4.0 * XD * XD * Y + 8.0 * X * (X + 1) / 2 * R2 + 2.0 * ncand * R2;
+          } else {
+            stats[4] += (double)ncand * pflops;
+          }
           stats[10] += 1;
           launch_apply_q(stream, d, cl, cr, st, q64, theta);
           launch_tableau_right_mult(stream, n, d, i, st, qinv, tx, tz, tp);

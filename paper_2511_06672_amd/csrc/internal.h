@@ -82,6 +82,8 @@ void set_error(const std::string& msg);
 #define GC_LAUNCH_CHECK() GC_HIP(hipGetLastError())
 
 // ----------------------------------------------------------------- limits
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
 constexpr int kMaxD = 7;
 constexpr int kMaxN = 128;
 constexpr int kSmallEig = 32;   // largest m handled by the single-workgroup eigensolver

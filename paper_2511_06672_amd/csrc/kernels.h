@@ -59,7 +59,8 @@ void launch_mpo_site(hipStream_t s, int kind, int d, int chil, int chir, int dx,
 void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* st, const z64* qmats,
                     z64* theta);
 // Candidate scores S2_c for the candidates cand_list[0..count) (or 0..count when cand_list is
-// null), in FP64 (prec 0) or FP32 (prec 1) arithmetic.  nlimit (nullable): device count that
+// null), in the arithmetic of `prec` (GCAMPS_SCORE_*; REPLICA takes the full set only and
+// needs replica_tables).  nlimit (nullable): device count that
 // overrides `count` (the list length is then only known on the device).  partial: scratch of
 // count * tiles doubles for the tiled path; nbuf: scratch for the rotated matrices of a chunk
 // of candidates (the tiled path processes as many candidates per launch as fit).  evs: optional
@@ -67,8 +68,23 @@ void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* s
 void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64* theta,
                   const z64* q64, const c32* q32, const int* cand_list, int count,
                   const int* nlimit, double* s2, double* partial, size_t partial_cap, void* nbuf,
-                  size_t nbuf_bytes, hipEvent_t* evs = nullptr, int evcap = 0, int* evused = nullptr);
+                  size_t nbuf_bytes, hipEvent_t* evs = nullptr, int evcap = 0, int* evused = nullptr,
+                  const z64* replica_tables = nullptr);
 void launch_select(hipStream_t s, int count, const double* s2, double tie_tol, DevStatus* st);
+
+// ------------------------------------------------------------------ replica scoring (kernels_replica.hip)
+// Full-set scores through the replica tensor of Theta (d = 2, 3): the Gram F of Theta over its
+// larger bond, the pair sum A, and one D^4 dot product per candidate with its table.
+constexpr int kReplicaMaxWg = 256;
+constexpr int kScoreSmallM = 96;    // matrices up to this many rows are scored directly (fused kernel)  // workgroups (partial sums) of the pair sum
+// complex128 elements of the tables of `count` candidates (left-cut and right-cut tables).
+size_t replica_table_elems(int d, int count);
+// Scratch bytes for bonds up to chi_max (F, the transposed Theta, partial sums, A).
+size_t replica_scratch_bytes(int d, int chi_max);
+// tables <- symmetrised V tables of the candidates qmats[0..count) (d^2 x d^2 unitaries).
+void launch_replica_tables(hipStream_t s, int d, int count, const z64* qmats, z64* tables);
+void launch_score_replica(hipStream_t s, int d, int chil, int chir, const z64* theta, const z64* tables,
+                          int count, double* s2, void* scratch, size_t scratch_bytes);
 // Low-precision window: list (ascending index) of candidates with s2lp <= min + window; the
 // list length goes to st->nwindow.
 void launch_window(hipStream_t s, int count, const double* s2lp, double window, int* list,

@@ -151,6 +151,7 @@ struct JacobiArgs {
   double tol;   // relative threshold |g| <= tol sqrt(|a b|) (rel mode)
   double skip;  // rel mode: pairs whose diagonal entries are both below skip are left alone
   int rel;
+  double floor2;  // rel mode: pairs with |g|^2 <= floor2 count as converged
 };
 
 // 1/sqrt(x) and 1/x from the hardware estimates refined by two Newton steps (the estimates
@@ -169,7 +170,8 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // Whether the pair with diagonal (a, b) and off-diagonal g = gr + i gi is rotated.
 __device__ __forceinline__ bool rot_needed(double a, double b, double gr, double gi, const JacobiArgs& ja) {
   const double h2 = gr * gr + gi * gi;
-  if (ja.rel) return h2 > 1e-290 && h2 > ja.tol * ja.tol * fabs(a) * fabs(b) && fmax(fabs(a), fabs(b)) > ja.skip;
+  if (ja.rel)
+    return h2 > 1e-290 && h2 > ja.floor2 && h2 > ja.tol * ja.tol * fabs(a) * fabs(b) && fmax(fabs(a), fabs(b)) > ja.skip;
   return h2 > 1e-290 && h2 > ja.thr * ja.thr;
 }
 
@@ -325,7 +327,8 @@ constexpr int SMALL_LD = 33;  // plane leading dimension for sub-problems of up 
 // Single-workgroup Jacobi: G (m x m, m <= kSmallEig = 32) -> U (m x m), lam (m), all in LDS.
 __global__ __launch_bounds__(256) void k_jacobi_small(const z64* __restrict__ G, int ldg_in, int m,
                                                       z64* __restrict__ U, int ldu, double* __restrict__ lam, int rel,
-                                                      double tol, double skip_rel, int max_sweeps, DevStatus* st) {
+                                                      double tol, double skip_rel, double floor_rel, int max_sweeps,
+                                                      DevStatus* st) {
   constexpr int PL = 32 * SMALL_LD;
   __shared__ double h0r[PL], h0i[PL], h1r[PL], h1i[PL], vr[PL], vi[PL];
   __shared__ unsigned char tab[31 * 32];
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(256) void k_jacobi_small(const z64* __restrict__ G,
     trace = tr;
   }
   __syncthreads();
-  const JacobiArgs ja{tol * trace, tol, skip_rel * trace, rel};
+  const JacobiArgs ja{tol * trace, tol, skip_rel * trace, rel, (floor_rel * trace) * (floor_rel * trace)};
   int sweeps = 0, cur = 0;
   bool conv = false;
   for (int sw = 0; sw < max_sweeps; ++sw) {
@@ -391,8 +394,9 @@ constexpr int SLD = BJ2 + 1;  // LDS leading dimension (plane layout)
 // block); later steps rotate only the 16 x 16 inter-block pairs.  Over one outer sweep every
 // index pair is visited once.
 __global__ __launch_bounds__(512) void k_jblock_solve(const z64* __restrict__ Gp, int mp, int nb, int step, double thr,
-                                                      double tol, double skip, int rel, z64* __restrict__ Vout,
-                                                      int* __restrict__ pair_flag, int* __restrict__ any_flag) {
+                                                      double tol, double skip, int rel, double floor2,
+                                                      z64* __restrict__ Vout, int* __restrict__ pair_flag,
+                                                      int* __restrict__ any_flag) {
   constexpr int PL = BJ2 * SLD;
   __shared__ double h0r[PL], h0i[PL], h1r[PL], h1i[PL], vr[PL], vi[PL];
   __shared__ unsigned char tab[31 * 32];
@@ -409,7 +413,7 @@ __global__ __launch_bounds__(512) void k_jblock_solve(const z64* __restrict__ Gp
     build_rr_table(tab, BJ2);
   else
     build_ib_table(tab, BJ);
-  const JacobiArgs ja{thr, tol, skip, rel};
+  const JacobiArgs ja{thr, tol, skip, rel, floor2};
   for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
     const int i = idx / BJ2, j = idx % BJ2;
     const int gi = (i < BJ ? I * BJ + i : J * BJ + (i - BJ));
@@ -800,10 +804,16 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   // sigma_0^2), so no decision depends on them, and exact null directions sit at the rounding
   // level (~1e-32 of the trace), where a relative criterion cannot be met.
   const double skip = rel ? 1e-28 / (double)m : 0.0;
+  // Relative pass: an off-diagonal entry of at most 1e-29 trace / m (<= 1e-29 lambda_max) counts
+  // as converged.  On exactly rank-deficient matrices the rounding of the rotations keeps
+  // entries of that size alive between directions at the rounding level, where a relative
+  // criterion is never met (the pass then ran out of sweeps); an eigenvalue at or above the rank
+  // floor (1e-26 lambda_max) moves by at most 1e-3 of itself because of such an entry.
+  const double floor_rel = rel ? 1e-29 / (double)m : 0.0;
   const int max_sweeps = 40;
   if (m <= kSmallEig) {
-    hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(256), 0, s, G, ldg, m, U, ldu, lam, rel, tol, skip, max_sweeps,
-                       st);
+    hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(256), 0, s, G, ldg, m, U, ldu, lam, rel, tol, skip, floor_rel,
+                       max_sweeps, st);
     GC_LAUNCH_CHECK();
     if (host_sweeps) *host_sweeps = -1;
     return;
@@ -821,7 +831,7 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   double trace = 0.0;
   GC_HIP(hipMemcpyAsync(&trace, d_trace, sizeof(double), hipMemcpyDeviceToHost, s));
   GC_HIP(hipStreamSynchronize(s));
-  const double thr = tol * trace, skipv = skip * trace;
+  const double thr = tol * trace, skipv = skip * trace, floor2 = (floor_rel * trace) * (floor_rel * trace);
   const size_t lds_b = 4 * (size_t)BJ2 * SLD * sizeof(double);
   const int half = nb / 2;
   int sweeps = 0;
@@ -829,7 +839,7 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   for (int sw = 0; sw < max_sweeps; ++sw) {
     GC_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
     for (int step = 0; step < nb - 1; ++step) {
-      hipLaunchKernelGGL(k_jblock_solve, dim3(half), dim3(kSolveThreads), 0, s, Gp, mp, nb, step, thr, tol, skipv, rel, w.V,
+      hipLaunchKernelGGL(k_jblock_solve, dim3(half), dim3(kSolveThreads), 0, s, Gp, mp, nb, step, thr, tol, skipv, rel, floor2, w.V,
                          w.flags + 1, w.flags);
       GC_LAUNCH_CHECK();
       int tiles = half * (half + 1) / 2 + (mp / BJ2) * half;

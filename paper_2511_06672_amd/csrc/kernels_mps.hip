@@ -111,7 +111,7 @@ __device__ __forceinline__ cx<T> nelem(int d, int chil, int chir, bool rows_firs
   return melem<T>(d, chir, theta, q, a, s1p, s2p, b);
 }
 
-constexpr int SMALL_M = 96;
+constexpr int SMALL_M = kScoreSmallM;
 constexpr int SMALL_KC = 32;
 constexpr int SMALL_THREADS = 512;
 constexpr int SMALL_PPT = (SMALL_M * (SMALL_M + 1) / 2 + SMALL_THREADS - 1) / SMALL_THREADS;
@@ -829,20 +829,27 @@ void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* s
 
 void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64* theta, const z64* q64, const c32* q32,
                   const int* list, int count, const int* nlimit, double* s2, double* partial, size_t partial_cap,
-                  void* nbuf, size_t nbuf_bytes, hipEvent_t* evs, int evcap, int* evused) {
+                  void* nbuf, size_t nbuf_bytes, hipEvent_t* evs, int evcap, int* evused, const z64* replica_tables) {
   if (evused) *evused = 0;
   if (count <= 0) return;
+  if (prec == GCAMPS_SCORE_REPLICA) GC_CHECK(list == nullptr && nlimit == nullptr, GCAMPS_EINVAL,
+                                             "replica scoring takes the full candidate set");
   const bool rows_first = chil * d <= d * chir;
   const int m = rows_first ? chil * d : d * chir;
   const int k = rows_first ? d * chir : chil * d;
   if (m <= SMALL_M) {
-    if (prec == GCAMPS_SCORE_FP64)
+    if (prec == GCAMPS_SCORE_FP64 || prec == GCAMPS_SCORE_REPLICA)
       hipLaunchKernelGGL(k_score_small<double>, dim3(count), dim3(SMALL_THREADS), 0, s, d, chil, chir, theta, q64,
                          q32, list, nlimit, s2);
     else
       hipLaunchKernelGGL(k_score_small<float>, dim3(count), dim3(SMALL_THREADS), 0, s, d, chil, chir, theta, q64, q32,
                          list, nlimit, s2);
     GC_LAUNCH_CHECK();
+    return;
+  }
+  if (prec == GCAMPS_SCORE_REPLICA) {
+    GC_CHECK(replica_tables != nullptr, GCAMPS_EINVAL, "replica scoring without candidate tables");
+    launch_score_replica(s, d, chil, chir, theta, replica_tables, count, s2, nbuf, nbuf_bytes);
     return;
   }
   if (prec == GCAMPS_SCORE_BF16) {

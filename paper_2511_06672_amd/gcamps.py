@@ -19,12 +19,12 @@ LIB_PATH = os.path.join(_HERE, "libgcamps.so")
 GCAMPS_OK = 0
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EWORKSPACE", -4: "ECAPACITY",
                 -5: "EDEVICE", -6: "ENUMERIC"}
-SCORE_FP64, SCORE_FP32, SCORE_BF16 = 0, 1, 2
+SCORE_FP64, SCORE_FP32, SCORE_BF16, SCORE_REPLICA = 0, 1, 2, 3
 
 SYMBOLS = [
     "gcamps_workspace_bytes", "gcamps_init", "gcamps_destroy", "gcamps_apply_clifford",
     "gcamps_apply_clifford_layer", "gcamps_apply_phase_rotation", "gcamps_candset_create",
-    "gcamps_candset_destroy", "gcamps_set_candset", "gcamps_disentangle", "gcamps_expectation",
+    "gcamps_candset_destroy", "gcamps_set_candset", "gcamps_score_bond", "gcamps_disentangle", "gcamps_expectation",
     "gcamps_statevector", "gcamps_amplitude", "gcamps_get_tableau", "gcamps_get_bond_dims",
     "gcamps_get_fidelity", "gcamps_get_choice_log", "gcamps_get_site", "gcamps_get_stats",
     "gcamps_batch_workspace_bytes", "gcamps_batch_run", "gcamps_grad_record", "gcamps_grad_loss",
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gcamps_candset_create": [I32, C.POINTER(CWord), I32, C.POINTER(P)],
         "gcamps_candset_destroy": [P],
         "gcamps_set_candset": [P, P],
+        "gcamps_score_bond": [P, I32, C.POINTER(D), I64],
         "gcamps_disentangle": [P, P, C.POINTER(I32), C.POINTER(I32)],
         "gcamps_expectation": [P, C.POINTER(C.c_int8), C.POINTER(C.c_int8), I32, C.POINTER(D)],
         "gcamps_statevector": [P, P, P, SZ],
@@ -222,6 +223,17 @@ class State:
     def set_candset(self, cs: CandSet):
         self._candset = cs
         _check(lib().gcamps_set_candset(self.handle, cs.handle))
+
+    def score_bond(self, bond: int) -> np.ndarray:
+        """S2 of every candidate of the attached set at bond (bond, bond + 1), in the
+        configured scoring mode (gcamps_score_bond); moves the orthogonality centre there."""
+        cs = getattr(self, "_candset", None)
+        if cs is None:
+            raise GcampsError("score_bond needs a candidate set attached with set_candset")
+        cnt = cs.count
+        buf = (C.c_double * cnt)()
+        _check(lib().gcamps_score_bond(self.handle, bond, buf, cnt))
+        return np.frombuffer(buf, dtype=np.float64).copy()
 
     def disentangle(self, cs: Optional[CandSet] = None):
         sw, ch = C.c_int32(0), C.c_int32(0)

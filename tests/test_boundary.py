@@ -40,6 +40,18 @@ def test_workspace_sizing_and_validation():
         assert e.value.code == -1
 
 
+def test_replica_mode_sizing_and_validation():
+    """Replica scoring: d = 2, 3 only; its workspace holds the candidate tables
+    (2 * N_c * d^8 complex128) and scratch for the Gram of Theta over chi_max d^2 rows."""
+    plain = g.workspace_bytes(g.make_config(3, 32, 256, 1e-10, score_prec=g.SCORE_FP32, max_candidates=512))
+    rep = g.workspace_bytes(g.make_config(3, 32, 256, 1e-10, score_prec=g.SCORE_REPLICA, max_candidates=512))
+    assert rep - plain >= 2 * 512 * 3 ** 8 * 16
+    assert g.workspace_bytes(g.make_config(2, 16, 64, 1e-10, score_prec=g.SCORE_REPLICA)) > 0
+    with pytest.raises(g.GcampsError) as e:
+        g.workspace_bytes(g.make_config(5, 8, 16, 0.0, score_prec=g.SCORE_REPLICA))
+    assert e.value.code == -2
+
+
 def test_candset_validation():
     cs = g.CandSet(3, candidate_words(3, 8, 3))
     assert cs.count == 8

@@ -24,7 +24,7 @@ def digest(tab):
     return hashlib.sha256(np.ascontiguousarray(tab, dtype="<i8").tobytes()).hexdigest()[:16]
 
 
-@pytest.mark.parametrize("prec", [2, 1, 0], ids=["bf16_scored", "fp32_scored", "fp64"])
+@pytest.mark.parametrize("prec", [3, 2, 1, 0], ids=["replica_scored", "bf16_scored", "fp32_scored", "fp64"])
 def test_headline_against_oracle_reference(prec):
     if not os.path.exists(GOLDEN):
         pytest.skip("oracle reference not generated")
