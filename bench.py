@@ -16,7 +16,9 @@ both must give identical choice logs and fidelity estimates.
 Beside the timed path the headline line carries the same circuit with split-BF16 scoring
 (`bf16_path`) and with replica-tensor scoring (`replica_path`: FP64 scores of all candidates
 from one Gram product of Theta per bond, an exact rewriting of the purity), each with its
-rate and whether its choice log equals the timed path's.
+rate and whether its choice log equals the timed path's, and the same circuit disentangled with
+the exhaustive set of §3 (90 unique qutrit disentanglers instead of 512 random words;
+`exhaustive_path`, with its own fidelity).
 
 A second workload measures batching of independent circuits (qutrits, circuit i with
 n_i ~ U{8..48} sites, T_i ~ U{4..60} T gates at uniform positions, 2 n_i layers,
@@ -84,13 +86,14 @@ def measured_traffic():
     return value if (want == src and value is not None) else None
 
 
-def run_circuit(g, wl, prec, progress=True):
+def run_circuit(g, wl, prec, progress=True, cands=None):
     import torch
     c = wl.circuit
+    cands = wl.candidates if cands is None else cands
     cfg = g.make_config(c.d, c.n, wl.chi_max, wl.cutoff, score_prec=prec, near_tie=NEAR_TIE,
-                        max_sweeps=wl.max_sweeps, max_candidates=len(wl.candidates))
+                        max_sweeps=wl.max_sweeps, max_candidates=len(cands))
     st = g.State(cfg)
-    st.set_candset(g.CandSet(c.d, wl.candidates))
+    st.set_candset(g.CandSet(c.d, cands))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gi = 0
@@ -340,6 +343,8 @@ def main():
     ap.add_argument("--score", choices=["fp32", "bf16"], default="fp32",
                     help="headline: precision of the timed path's candidate scoring")
     ap.add_argument("--no-bf16", action="store_true", help="headline: skip the split-BF16 comparison run")
+    ap.add_argument("--no-exhaustive", action="store_true",
+                    help="headline: skip the run with the exhaustive disentangler set")
     ap.add_argument("--no-replica", action="store_true",
                     help="headline: skip the replica-tensor-scored comparison run")
     args = ap.parse_args()
@@ -420,6 +425,15 @@ def main():
                   "scoring_gflop": sr["score_flops"] / 1e9,
                   "rescored_candidates": int(sr["rescored"])}
 
+    resex = None
+    if not args.no_exhaustive:
+        words = g.clifford_words(c.d, g.WORDS_DISENTANGLERS)
+        log(f"exhaustive disentangler set ({len(words)} words), FP32-scored (same circuit)")
+        ste, te = run_circuit(g, wl, g.SCORE_FP32, cands=words)
+        resex = {"value": ngates / te, "ms_per_step": 1e3 * te, "candidates": len(words),
+                 "fidelity": ste.fidelity(), "final_bond_dim_max": int(max(ste.bond_dims())),
+                 "fidelity_vs_timed_path": ste.fidelity() / st32.fidelity()}
+
     # roofline of the Gram-purity MFMA kernel, timed per launch with HIP events
     tiled_ms = s32["tiled_ms"]
     roof = None
@@ -468,6 +482,7 @@ def main():
         "speedup_vs_fp64": (res64["ms_per_step"] / (1e3 * t32)) if res64 else None,
         "bf16_path": resbf,
         "replica_path": resrep,
+        "exhaustive_path": resex,
         "rescored_candidates": int(s32["rescored"]),
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -132,6 +132,21 @@ int32_t gcamps_apply_phase_rotation(gcamps_ctx* ctx, int32_t site, const double*
 /* Compile candidate disentanglers (§3: two-qudit Cliffords Q whose application
  * to the MPS is compensated by C <- C Q^dagger).  words[0] must be the identity
  * (len 0, zero Weyl shift).  Host object; count >= 1. Errors: EINVAL. */
+/* Exhaustive two-qudit Clifford sets as generator words (§3, §3.1), without Weyl shifts, the
+ * identity first.  Up to Weyl shifts a pair Clifford is its 4x4 symplectic matrix over Z_d.
+ *   GCAMPS_WORDS_DISENTANGLERS: one word per class of Cliffords that differ only by
+ *     single-qudit Cliffords applied after them, which leave the entanglement unchanged: the
+ *     unique disentanglers of §3 (20 for d = 2, 90 for d = 3), each a shortest word of its class.
+ *   GCAMPS_WORDS_ALL: one word per element of Sp(4, Z_d) (720 for d = 2, 51840 for d = 3).
+ * Outputs (host memory): lens[i] = length of word i, gens = the words' generator codes
+ * concatenated (application order, codes as in gcamps_word).  With lens == NULL only *count
+ * and *total_gens are written.  The words feed gcamps_candset_create directly.
+ * Errors: EINVAL (unknown kind, null count/total_gens, capacities below the set),
+ * EUNSUPPORTED (d other than 2 and 3: §3.1 leaves larger d out, the group grows as d^10). */
+enum { GCAMPS_WORDS_DISENTANGLERS = 0, GCAMPS_WORDS_ALL = 1 };
+int32_t gcamps_clifford_words(int32_t d, int32_t kind, int32_t* lens, int32_t lens_cap, uint8_t* gens,
+                              int64_t gens_cap, int32_t* count, int64_t* total_gens);
+
 int32_t gcamps_candset_create(int32_t d, const gcamps_word* words, int32_t count,
                               gcamps_candset** out);
 int32_t gcamps_candset_destroy(gcamps_candset* set);

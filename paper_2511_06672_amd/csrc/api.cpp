@@ -300,6 +300,26 @@ int32_t gcamps_apply_phase_rotation(gcamps_ctx* ctx, int32_t site, const double*
   });
 }
 
+int32_t gcamps_clifford_words(int32_t d, int32_t kind, int32_t* lens, int32_t lens_cap, uint8_t* gens,
+                              int64_t gens_cap, int32_t* count, int64_t* total_gens) {
+  return guarded(nullptr, [&] {
+    GC_CHECK(count && total_gens, GCAMPS_EINVAL, "null argument");
+    const auto words = clifford_word_set(d, kind);
+    int64_t total = 0;
+    for (const auto& w : words) total += (int64_t)w.size();
+    *count = (int32_t)words.size();
+    *total_gens = total;
+    if (!lens) return;
+    GC_CHECK(lens_cap >= (int32_t)words.size() && gens_cap >= total && (total == 0 || gens), GCAMPS_EINVAL,
+             "output capacity below the word set");
+    int64_t o = 0;
+    for (size_t i = 0; i < words.size(); ++i) {
+      lens[i] = (int32_t)words[i].size();
+      for (uint8_t g : words[i]) gens[o++] = g;
+    }
+  });
+}
+
 int32_t gcamps_candset_create(int32_t d, const gcamps_word* words, int32_t count, gcamps_candset** out) {
   return guarded(nullptr, [&] {
     GC_CHECK(out && words && count >= 1, GCAMPS_EINVAL, "null argument or empty set");

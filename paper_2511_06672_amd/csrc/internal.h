@@ -127,6 +127,8 @@ struct CompiledWord {
   std::vector<z64> mat;       // d^2 x d^2 unitary, row-major (row = s_a*d + s_b)
 };
 CompiledWord compile_word(int d, const gcamps_word& w);
+// Generator words (application order) of an exhaustive two-qudit Clifford set, identity first.
+std::vector<std::vector<uint8_t>> clifford_word_set(int d, int kind);
 
 }  // namespace gc
 

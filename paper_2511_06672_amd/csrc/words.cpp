@@ -12,8 +12,10 @@
 // The inverse table (U^dagger W U) is the inverse permutation with negated
 // phase increments.  The dense d^2 x d^2 unitary is the ordered product of the
 // §2.3 gate matrices.
+#include <array>
 #include <cmath>
 #include <complex>
+#include <unordered_set>
 
 #include "internal.h"
 
@@ -151,6 +153,97 @@ CompiledWord compile_word(int d, const gcamps_word& w) {
   cw.mat.resize(D * D);
   for (int i = 0; i < D * D; ++i) cw.mat[i] = z64{u[i].real(), u[i].imag()};
   return cw;
+}
+
+// ----------------------------------------------------------------- exhaustive word sets
+// Up to Weyl shifts and phases a two-qudit Clifford is the 4x4 matrix over Z_d of its
+// conjugation action on the exponents (x_a, z_a, x_b, z_b) (the phase-free part of the rules
+// above); S_{Q2 Q1} = S_{Q2} S_{Q1}.  Single-qudit Cliffords L applied after Q leave the
+// entanglement of Q|psi> unchanged (§3.1), so the disentanglers are the classes {L Q}.  These
+// classes are permuted by right multiplication with the generators (S -> S S_g: g applied
+// before Q), so a breadth-first search over classes from the identity, each class keyed by
+// its smallest member L S (base-d number of the entries, row by row), visits every class once
+// and labels it with a shortest word.  The whole group is enumerated the same way with the
+// matrix itself as the key.
+namespace {
+
+using Sym = std::array<uint8_t, 16>;  // row-major 4 x 4 over Z_d
+
+Sym sym_identity() {
+  Sym s{};
+  for (int i = 0; i < 4; ++i) s[i * 5] = 1;
+  return s;
+}
+
+Sym sym_of_generator(int d, int g) {
+  Sym s{};
+  for (int c = 0; c < 4; ++c) {
+    W2 w{c == 0, c == 1, c == 2, c == 3, 0};
+    apply_gen(d, w, g);
+    s[0 * 4 + c] = (uint8_t)w.xa;
+    s[1 * 4 + c] = (uint8_t)w.za;
+    s[2 * 4 + c] = (uint8_t)w.xb;
+    s[3 * 4 + c] = (uint8_t)w.zb;
+  }
+  return s;
+}
+
+Sym sym_mul(int d, const Sym& a, const Sym& b) {
+  Sym c{};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      int acc = 0;
+      for (int k = 0; k < 4; ++k) acc += a[i * 4 + k] * b[k * 4 + j];
+      c[i * 4 + j] = (uint8_t)(acc % d);
+    }
+  return c;
+}
+
+uint64_t sym_code(int d, const Sym& s) {
+  uint64_t v = 0;
+  for (int i = 0; i < 16; ++i) v = v * (uint64_t)d + s[i];
+  return v;
+}
+
+}  // namespace
+
+std::vector<std::vector<uint8_t>> clifford_word_set(int d, int kind) {
+  GC_CHECK(d == 2 || d == 3, GCAMPS_EUNSUPPORTED, "exhaustive Clifford sets are built for d = 2 and 3");
+  GC_CHECK(kind == GCAMPS_WORDS_DISENTANGLERS || kind == GCAMPS_WORDS_ALL, GCAMPS_EINVAL, "unknown word-set kind");
+  Sym gen[6];
+  for (int g = 0; g < 6; ++g) gen[g] = sym_of_generator(d, g);
+  // single-qudit Cliffords: the group generated by F and P on either site
+  std::vector<Sym> local{sym_identity()};
+  {
+    std::unordered_set<uint64_t> seen{sym_code(d, local[0])};
+    for (size_t i = 0; i < local.size(); ++i)
+      for (int g = 0; g < 4; ++g) {
+        const Sym t = sym_mul(d, gen[g], local[i]);
+        if (seen.insert(sym_code(d, t)).second) local.push_back(t);
+      }
+  }
+  auto key = [&](const Sym& s) {
+    if (kind == GCAMPS_WORDS_ALL) return sym_code(d, s);
+    uint64_t best = UINT64_MAX;
+    for (const Sym& l : local) best = std::min(best, sym_code(d, sym_mul(d, l, s)));
+    return best;
+  };
+  std::vector<std::vector<uint8_t>> words{{}};
+  std::vector<Sym> reps{sym_identity()};
+  std::unordered_set<uint64_t> seen{key(reps[0])};
+  for (size_t i = 0; i < reps.size(); ++i)
+    for (int g = 0; g < 6; ++g) {
+      const Sym t = sym_mul(d, reps[i], gen[g]);
+      if (seen.insert(key(t)).second) {
+        std::vector<uint8_t> w;
+        w.reserve(words[i].size() + 1);
+        w.push_back((uint8_t)g);
+        w.insert(w.end(), words[i].begin(), words[i].end());
+        words.push_back(std::move(w));
+        reps.push_back(t);
+      }
+    }
+  return words;
 }
 
 }  // namespace gc

@@ -20,11 +20,12 @@ GCAMPS_OK = 0
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EWORKSPACE", -4: "ECAPACITY",
                 -5: "EDEVICE", -6: "ENUMERIC"}
 SCORE_FP64, SCORE_FP32, SCORE_BF16, SCORE_REPLICA = 0, 1, 2, 3
+WORDS_DISENTANGLERS, WORDS_ALL = 0, 1
 
 SYMBOLS = [
     "gcamps_workspace_bytes", "gcamps_init", "gcamps_destroy", "gcamps_apply_clifford",
     "gcamps_apply_clifford_layer", "gcamps_apply_phase_rotation", "gcamps_candset_create",
-    "gcamps_candset_destroy", "gcamps_set_candset", "gcamps_score_bond", "gcamps_disentangle", "gcamps_expectation",
+    "gcamps_candset_destroy", "gcamps_clifford_words", "gcamps_set_candset", "gcamps_score_bond", "gcamps_disentangle", "gcamps_expectation",
     "gcamps_statevector", "gcamps_amplitude", "gcamps_get_tableau", "gcamps_get_bond_dims",
     "gcamps_get_fidelity", "gcamps_get_choice_log", "gcamps_get_site", "gcamps_get_stats",
     "gcamps_batch_workspace_bytes", "gcamps_batch_run", "gcamps_grad_record", "gcamps_grad_loss",
@@ -90,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gcamps_candset_destroy": [P],
         "gcamps_set_candset": [P, P],
         "gcamps_score_bond": [P, I32, C.POINTER(D), I64],
+        "gcamps_clifford_words": [I32, I32, C.POINTER(I32), I32, C.POINTER(C.c_uint8), I64, C.POINTER(I32),
+                                  C.POINTER(I64)],
         "gcamps_disentangle": [P, P, C.POINTER(I32), C.POINTER(I32)],
         "gcamps_expectation": [P, C.POINTER(C.c_int8), C.POINTER(C.c_int8), I32, C.POINTER(D)],
         "gcamps_statevector": [P, P, P, SZ],
@@ -157,6 +160,22 @@ def workspace_bytes(cfg: Config) -> int:
     b = C.c_size_t(0)
     _check(lib().gcamps_workspace_bytes(C.byref(cfg), C.byref(b)))
     return b.value
+
+
+def clifford_words(d: int, kind: int = WORDS_DISENTANGLERS):
+    """Exhaustive two-qudit Clifford set as Word objects (gcamps_clifford_words): the unique
+    disentanglers (kind WORDS_DISENTANGLERS) or all of Sp(4, Z_d) (WORDS_ALL), identity first."""
+    from .workload import Word
+    cnt, tot = C.c_int32(0), C.c_int64(0)
+    _check(lib().gcamps_clifford_words(d, kind, None, 0, None, 0, C.byref(cnt), C.byref(tot)))
+    lens = (C.c_int32 * max(1, cnt.value))()
+    gens = (C.c_uint8 * max(1, tot.value))()
+    _check(lib().gcamps_clifford_words(d, kind, lens, cnt.value, gens, tot.value, C.byref(cnt), C.byref(tot)))
+    out, o = [], 0
+    for i in range(cnt.value):
+        out.append(Word(tuple(int(g) for g in gens[o:o + lens[i]]), (0, 0, 0, 0)))
+        o += lens[i]
+    return out
 
 
 class CandSet:
