@@ -27,6 +27,16 @@ RANK_FLOOR = 1e-13
 DEGENERACY = 1e-10
 
 
+def svd(a: np.ndarray):
+    """Thin SVD (LAPACK).  The divide-and-conquer driver occasionally fails to converge; the
+    QR-iteration driver then computes the same decomposition."""
+    try:
+        return np.linalg.svd(a, full_matrices=False)
+    except np.linalg.LinAlgError:
+        import scipy.linalg
+        return scipy.linalg.svd(a, full_matrices=False, lapack_driver="gesvd")
+
+
 def rtrunc(sigma: np.ndarray, cutoff: float, chi_max: int,
            floor: float = RANK_FLOOR, degen: float = DEGENERACY) -> Tuple[int, float, bool]:
     """Apply R-TRUNC to singular values ``sigma`` (descending).  Returns (k, eps, flagged)."""
@@ -132,7 +142,7 @@ class MPS:
         discarded weight of that rank.
         """
         cl, d, _, cr = theta.shape
-        u, s, vh = np.linalg.svd(theta.reshape(cl * d, d * cr), full_matrices=False)
+        u, s, vh = svd(theta.reshape(cl * d, d * cr))
         k, eps, flagged = rtrunc(s, cutoff, chi_max)
         if force_k is not None:
             k, flagged = int(force_k), False
@@ -164,7 +174,7 @@ class MPS:
         for t, i in enumerate(range(r, l, -1)):
             a = self.tensors[i]
             cl, d, cr = a.shape
-            u, s, vh = np.linalg.svd(a.reshape(cl, d * cr), full_matrices=False)
+            u, s, vh = svd(a.reshape(cl, d * cr))
             k, eps, flagged = rtrunc(s, cutoff, chi_max)
             if force_ks is not None:
                 k, flagged = int(force_ks[t]), False

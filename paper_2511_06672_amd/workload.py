@@ -198,6 +198,9 @@ class Workload:
     chi_max: int
     cutoff: float
     max_sweeps: int = 2
+    # "listed": `candidates` is the set; "all_sp4": every two-qudit Clifford up to Weyl shifts
+    # (720 for qubits), enumerated by the caller (this module holds no Clifford arithmetic)
+    candidate_set: str = "listed"
 
 
 def workload(name: str, n: int | None = None) -> Workload:
@@ -220,6 +223,22 @@ def workload(name: str, n: int | None = None) -> Workload:
         c = brickwork_circuit(3, nn, 2 * nn, 32, seed, one_per_layer=False,
                               parametrised=True)
         return Workload(name, c, candidate_words(3, 512, seed), chi_max=256, cutoff=1e-10)
+    if name == "mixed_d2_n64":
+        # mixed run, qubit part: one T = diag(1, e^{i pi/4}) per layer, chi_max 1024, cutoff
+        # 1e-12, the 720 elements of Sp(4, Z_2) as candidates
+        nn = 64 if n is None else n
+        seed = 3001
+        layers = 64 if n is None else nn
+        c = brickwork_circuit(2, nn, layers, layers, seed)
+        return Workload(name, c, [], chi_max=1024, cutoff=1e-12, candidate_set="all_sp4")
+    if name == "mixed_d3_n48":
+        # mixed run, qutrit part: 60 layers with one T each, chi_max 1024, cutoff 1e-12,
+        # identity + 719 seeded random candidates
+        nn = 48 if n is None else n
+        seed = 3002
+        layers = 60 if n is None else max(8, (60 * nn) // 48)
+        c = brickwork_circuit(3, nn, layers, layers, seed)
+        return Workload(name, c, candidate_words(3, 720, seed), chi_max=1024, cutoff=1e-12)
     raise KeyError(name)
 
 

@@ -1,0 +1,69 @@
+"""Parity on the mixed-run workloads (qubits: n = 64, 64 layers, one T per layer, the 720
+elements of Sp(4, Z_2) as candidates; qutrits: n = 48, 60 layers, one T per layer, identity +
+719 random candidates; chi_max = 1024, cutoff 1e-12 for both), with split-BF16 scoring and the
+FP64 window re-score as configured, and with plain FP64 scoring.
+
+Expected values come from tests/golden/mixed_d{2,3}_*_oracle.json, written by
+tests/golden/make_mixed_reference.py, which calls only the oracle.  Compared gate by gate over
+the gates the reference covers: choices, bond dimensions and tableau bit-exact, F_est relative
+F_TOL (as for the other references).  The qubit candidate list is the oracle's enumeration of
+Sp(4, Z_2), passed to both sides.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+F_TOL = 1e-9
+
+
+def digest(tab):
+    return hashlib.sha256(np.ascontiguousarray(tab, dtype="<i8").tobytes()).hexdigest()[:16]
+
+
+@pytest.mark.parametrize("name", ["mixed_d2_n64", "mixed_d3_n48"])
+@pytest.mark.parametrize("prec", [2, 0], ids=["bf16_scored", "fp64"])
+def test_mixed_run_against_oracle_reference(name, prec):
+    path = os.path.join(GOLDEN, f"{name}_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle reference not generated")
+    ref = json.load(open(path))
+    import torch
+    from oracle.disentanglers import all_cliffords
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import Word, workload
+    assert torch.cuda.is_available()
+    wl = workload(name)
+    c = wl.circuit
+    cands = ([Word(w, (0, 0, 0, 0)) for w, _ in all_cliffords(c.d)] if wl.candidate_set == "all_sp4"
+             else wl.candidates)
+    assert len(cands) == ref["candidates"] == 720
+    ngates = ref["gates_done"]
+    print(f"[gpu-case] {name}, {ngates} gates, prec={prec}", flush=True)
+    st = g.State(g.make_config(c.d, c.n, wl.chi_max, wl.cutoff, score_prec=prec, near_tie=1e-4,
+                               max_candidates=len(cands)))
+    st.set_candset(g.CandSet(c.d, cands))
+    gi = 0
+    prev = 0
+    for layer in c.layers:
+        if gi >= ngates:
+            break
+        if layer.bricks:
+            st.apply_clifford_layer([b.site for b in layer.bricks], [b.word for b in layer.bricks])
+        for ph in layer.phases:
+            st.apply_phase_rotation(ph.site, ph.phi)
+            r = ref["gates"][gi]
+            log = st.choice_log()
+            mine = log[prev:]
+            prev = len(log)
+            assert [list(map(int, x[1:])) for x in mine] == r["choices"], f"choices differ at gate {gi}"
+            assert st.bond_dims() == r["bond_dims"], f"bond dims differ at gate {gi}"
+            assert digest(st.tableau()) == r["tableau_sha256"], f"tableau differs at gate {gi}"
+            assert abs(st.fidelity() - r["f_est"]) <= F_TOL * r["f_est"], f"fidelity differs at gate {gi}"
+            gi += 1
+    assert gi == ngates
