@@ -810,7 +810,10 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   // criterion is never met (the pass then ran out of sweeps); an eigenvalue at or above the rank
   // floor (1e-26 lambda_max) moves by at most 1e-3 of itself because of such an entry.
   const double floor_rel = rel ? 1e-29 / (double)m : 0.0;
-  const int max_sweeps = 40;
+  // Sweeps grow with m on these Grams: up to ~20 at m = 768, 19-26 at m = 3072, where one
+  // decomposition needed more than 40 (every sub-problem still rotating for the first ~20
+  // sweeps, then a steady decay).
+  const int max_sweeps = m > 1024 ? 100 : 40;
   if (m <= kSmallEig) {
     hipLaunchKernelGGL(k_jacobi_small, dim3(1), dim3(256), 0, s, G, ldg, m, U, ldu, lam, rel, tol, skip, floor_rel,
                        max_sweeps, st);
