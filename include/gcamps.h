@@ -82,6 +82,9 @@ typedef struct {
   int32_t max_sweeps;       /* disentangling sweeps per non-Clifford gate (default 2) */
   int32_t auto_disentangle; /* 1: gcamps_apply_phase_rotation disentangles afterwards */
   int32_t max_candidates;   /* capacity of the candidate table (>= candidate count) */
+  int32_t max_gate_terms;   /* largest number of Weyl terms of a gcamps_apply_gate unitary (its MPO
+                               bond, 1..81); 0 means d (diagonal phase gates only).  Bond
+                               capacity is chi_max * max(d, max_gate_terms) <= 4096. */
 } gcamps_config;
 
 /* A two-qudit Clifford word on the ordered pair (a, b) = (site, site + 1):
@@ -146,6 +149,20 @@ int32_t gcamps_apply_phase_rotation(gcamps_ctx* ctx, int32_t site, const double*
 enum { GCAMPS_WORDS_DISENTANGLERS = 0, GCAMPS_WORDS_ALL = 1 };
 int32_t gcamps_clifford_words(int32_t d, int32_t kind, int32_t* lens, int32_t lens_cap, uint8_t* gens,
                               int64_t gens_cap, int32_t* count, int64_t* total_gens);
+
+/* Apply a general non-Clifford gate U on `nsites` (1 or 2) adjacent qudits site..site+nsites-1
+ * (the bottom loop of §3 for a unitary that is not diagonal or acts on two sites).  U is
+ * d^k x d^k (k = nsites), row-major complex128 as interleaved (re, im), digit order with site
+ * `site` most significant.  U is expanded on the Weyl basis, U = sum_{x,z} c_xz W_xz with
+ * W_xz = (x)_t X^{x_t} Z^{z_t} and c_xz = Tr(W_xz^dagger U) / d^k (§2.3: the Weyl operators are
+ * an orthogonal operator basis); terms with |c| <= 1e-14 max|c| are dropped.  Each kept term is
+ * commuted through the Clifford (§2.3.1, as for Z_k in gcamps_apply_phase_rotation) and the sum
+ * is applied to the MPS as an MPO whose bond is the number J of kept terms, then compressed
+ * (§2.4) and, with auto_disentangle, disentangled (§3).  Diagonal single-site U gives the same
+ * state as gcamps_apply_phase_rotation.
+ * Errors: EINVAL (null pointer, site or nsites out of range, U not unitary to 1e-10),
+ * ECAPACITY (J > max(d, max_gate_terms)), ENUMERIC, EDEVICE. */
+int32_t gcamps_apply_gate(gcamps_ctx* ctx, int32_t site, int32_t nsites, const double* u);
 
 int32_t gcamps_candset_create(int32_t d, const gcamps_word* words, int32_t count,
                               gcamps_candset** out);

@@ -48,6 +48,22 @@ def diagonal_coefficients(d: int, phi: Sequence[float]) -> np.ndarray:
     return np.linalg.solve(V, np.exp(1j * np.asarray(phi, dtype=np.float64)))
 
 
+def weyl_expansion(d: int, k: int, u: np.ndarray, drop: float = 1e-14):
+    """U = sum_{x,z} c_xz W_xz on k sites, W_xz = (x)_t X^{x_t} Z^{z_t} (§2.3: the d^{2k} Weyl
+    operators are orthogonal, Tr(W^dagger W') = d^k delta), so c_xz = Tr(W_xz^dagger U) / d^k.
+    Returns [(x, z, c)] for |c| > drop * max|c|, x and z tuples over the k sites."""
+    from itertools import product
+    terms = []
+    for x in product(range(d), repeat=k):
+        for z in product(range(d), repeat=k):
+            w = np.ones((1, 1))
+            for t in range(k):
+                w = np.kron(w, site_matrix(d, x[t], z[t]))
+            terms.append((x, z, np.trace(w.conj().T @ u) / d ** k))
+    cmax = max(abs(c) for _, _, c in terms)
+    return [t for t in terms if abs(t[2]) > drop * cmax]
+
+
 def renyi2(theta: np.ndarray) -> float:
     """S2 across the middle cut of a two-site tensor (chi_l, d, d, chi_r), direct definition."""
     cl, d, _, cr = theta.shape
@@ -137,6 +153,39 @@ class Gcamps:
                 force = [self._frozen_ranks.pop(0) for _ in range(r - l)]
             epss, flags = self.mps.truncate_sweep_left(l, r, self.cfg.cutoff, self.cfg.chi_max,
                                                        force_ks=force)
+            self.rank_log.extend(self.mps.last_ks)
+            for e in epss:
+                self.f_est *= (1.0 - e)
+            self.flags += sum(flags)
+        self.gate_count += 1
+        if self.cfg.auto_disentangle and self.candidates:
+            self.disentangle()
+
+    def apply_gate(self, site: int, u: np.ndarray):
+        """A general gate U on sites site..site+k-1 (the bottom loop for a non-diagonal or
+        two-site unitary): every Weyl term of U is commuted through C by elimination (§2.3.1),
+        the sum is applied as a block MPO with one block per term, then compressed (§2.4) and
+        disentangled (§3)."""
+        d, n = self.d, self.n
+        k = 1 if u.shape[0] == d else 2
+        terms = weyl_expansion(d, k, u)
+        Ps, coeff = [], []
+        for x, z, c in terms:
+            xs = np.zeros(n, np.int64)
+            zs = np.zeros(n, np.int64)
+            xs[site:site + k] = x
+            zs[site:site + k] = z
+            P, _, _ = self.tab.decompose(Weyl(d, xs, zs, 0))
+            Ps.append(P)
+            coeff.append(c * tau(d) ** P.p)
+        sup = [i for i in range(n) if any(P.x[i] or P.z[i] for P in Ps)]
+        l, r = (sup[0], sup[-1]) if sup else (site, site)
+        self.last_support = (l, r)
+        ops = [[site_matrix(d, int(P.x[i]), int(P.z[i])) for i in range(l, r + 1)] for P in Ps]
+        self.mps.move_centre(l)
+        self.mps.apply_block_mpo(l, r, ops, np.array(coeff))
+        if r > l:
+            epss, flags = self.mps.truncate_sweep_left(l, r, self.cfg.cutoff, self.cfg.chi_max)
             self.rank_log.extend(self.mps.last_ks)
             for e in epss:
                 self.f_est *= (1.0 - e)

@@ -40,7 +40,10 @@ void validate_config(const gcamps_config* c) {
   GC_CHECK(c->d >= 2 && c->d <= kMaxD, GCAMPS_EINVAL, "d out of range [2, 7]");
   GC_CHECK(is_prime(c->d), GCAMPS_EUNSUPPORTED, "d must be prime (decomposition over the field Z_d)");
   GC_CHECK(c->n >= 2 && c->n <= kMaxN, GCAMPS_EINVAL, "n out of range [2, 128]");
-  GC_CHECK(c->chi_max >= 1 && (size_t)c->chi_max * c->d <= 4096, GCAMPS_EINVAL, "chi_max out of range");
+  GC_CHECK(c->max_gate_terms >= 0 && c->max_gate_terms <= kMaxGateTerms, GCAMPS_EINVAL,
+           "max_gate_terms out of range [0, 81]");
+  GC_CHECK(c->chi_max >= 1 && (size_t)c->chi_max * std::max(c->d, c->max_gate_terms) <= 4096, GCAMPS_EINVAL,
+           "chi_max out of range (chi_max * max(d, max_gate_terms) must not exceed 4096)");
   GC_CHECK(c->cutoff >= 0.0 && c->cutoff < 1.0, GCAMPS_EINVAL, "cutoff out of range [0, 1)");
   GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->score_prec == GCAMPS_SCORE_FP32 ||
                c->score_prec == GCAMPS_SCORE_BF16 || c->score_prec == GCAMPS_SCORE_REPLICA,
@@ -90,7 +93,8 @@ namespace gc {
 Layout make_layout(const gcamps_config& c) {
   Layout L{};
   const size_t d = c.d, chi = c.chi_max;
-  const size_t chicap = chi * d;
+  // bond capacity: an MPO of bond J = max(d, max_gate_terms) multiplies bonds by J before compression
+  const size_t chicap = chi * std::max<size_t>(d, (size_t)c.max_gate_terms);
   L.slot_elems = chicap * d * chicap;
   L.theta_elems = chi * d * d * chi;
   L.mcap = chicap;
@@ -317,6 +321,34 @@ int32_t gcamps_clifford_words(int32_t d, int32_t kind, int32_t* lens, int32_t le
       lens[i] = (int32_t)words[i].size();
       for (uint8_t g : words[i]) gens[o++] = g;
     }
+  });
+}
+
+int32_t gcamps_apply_gate(gcamps_ctx* ctx, int32_t site, int32_t nsites, const double* u) {
+  return guarded(ctx, [&] {
+    GC_CHECK(ctx && u, GCAMPS_EINVAL, "null argument");
+    GC_CHECK(nsites == 1 || nsites == 2, GCAMPS_EINVAL, "nsites must be 1 or 2");
+    GC_CHECK(site >= 0 && site + nsites <= ctx->n, GCAMPS_EINVAL, "gate sites out of range");
+    int D = 1;
+    for (int t = 0; t < nsites; ++t) D *= ctx->d;
+    std::vector<z64> U((size_t)D * D);
+    for (size_t i = 0; i < U.size(); ++i) {
+      U[i] = z64{u[2 * i], u[2 * i + 1]};
+      GC_CHECK(std::isfinite(U[i].re) && std::isfinite(U[i].im), GCAMPS_EINVAL, "gate entry not finite");
+    }
+    for (int i = 0; i < D; ++i)  // U^dagger U = I
+      for (int j = 0; j < D; ++j) {
+        double re = 0.0, im = 0.0;
+        for (int r = 0; r < D; ++r) {
+          const z64 a = U[(size_t)r * D + i], b = U[(size_t)r * D + j];
+          re += a.re * b.re + a.im * b.im;
+          im += a.re * b.im - a.im * b.re;
+        }
+        GC_CHECK(std::fabs(re - (i == j ? 1.0 : 0.0)) < 1e-10 && std::fabs(im) < 1e-10, GCAMPS_EINVAL,
+                 "gate is not unitary");
+      }
+    ctx->general_gate(site, nsites, U);
+    if (ctx->cfg.auto_disentangle && ctx->ncand > 0) ctx->disentangle(nullptr, nullptr);
   });
 }
 

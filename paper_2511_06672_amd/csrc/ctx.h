@@ -368,6 +368,14 @@ struct gcamps_ctx {
       std::swap(site[i], spare);
     }
     for (int j = l + 1; j <= r; ++j) chi[j] *= d;
+    compress(l, r);
+    gates += 1;
+    stats[0] += 1;
+  }
+
+  // After an MPO on [l, r] (centre at l): exact moves to r, then truncating splits back to l
+  // (§2.4); F_est absorbs the discarded weights.
+  void compress(int l, int r) {
     if (r > l) {
       for (int i = l; i < r; ++i) move_right(i);
       for (int i = r; i > l; --i) {
@@ -385,6 +393,96 @@ struct gcamps_ctx {
         stats[3] += h.flagged;
       }
     }
+  }
+
+  // General gate U on sites s..s+k-1 (k = 1, 2): Weyl expansion, each term commuted through the
+  // Clifford, the sum applied as an MPO of bond J = number of terms, then compressed.
+  void general_gate(int s, int k, const std::vector<z64>& U) {
+    GC_CHECK(tape == nullptr && rank_rec == nullptr && rank_frz == nullptr, GCAMPS_EUNSUPPORTED,
+             "general gates are not recorded for gradients");
+    int D = 1;
+    for (int t = 0; t < k; ++t) D *= d;
+    // c_xz = Tr(W_xz^dagger U) / D with W_xz |v> = omega^{z . v} |v + x> (digits of site s first)
+    struct Term {
+      std::vector<int> x, z;
+      std::complex<double> c;
+    };
+    std::vector<Term> terms;
+    double cmax = 0.0;
+    const int nx = D;  // exponent vectors x (and z) enumerate like basis states
+    auto digits = [&](int v, std::vector<int>& out) {
+      out.assign(k, 0);
+      for (int t = k - 1; t >= 0; --t) {
+        out[t] = v % d;
+        v /= d;
+      }
+    };
+    std::vector<int> xv, zv, sv, tv;
+    for (int xi = 0; xi < nx; ++xi)
+      for (int zi = 0; zi < nx; ++zi) {
+        digits(xi, xv);
+        digits(zi, zv);
+        std::complex<double> acc = 0.0;
+        for (int v = 0; v < D; ++v) {
+          digits(v, sv);
+          int row = 0, dot = 0;
+          for (int t = 0; t < k; ++t) {
+            row = row * d + (sv[t] + xv[t]) % d;
+            dot += zv[t] * sv[t];
+          }
+          const z64 uv = U[(size_t)row * D + v];  // <v + x| U |v>
+          acc += std::polar(1.0, -2.0 * M_PI * (double)(dot % d) / d) * std::complex<double>(uv.re, uv.im);
+        }
+        acc /= (double)D;
+        cmax = std::max(cmax, std::abs(acc));
+        terms.push_back({xv, zv, acc});
+      }
+    std::vector<Term> kept;
+    for (auto& t : terms)
+      if (std::abs(t.c) > 1e-14 * cmax) kept.push_back(t);
+    const int J = (int)kept.size();
+    GC_CHECK(J <= std::max(d, cfg.max_gate_terms), GCAMPS_ECAPACITY,
+             "gate has " + std::to_string(J) + " Weyl terms; raise max_gate_terms");
+    // commute every term through C: P_j = C^dagger W_j C
+    std::vector<GateRec> P(J);
+    int l = n, r = -1;
+    for (int j = 0; j < J; ++j) {
+      bool ident = true;
+      for (int t = 0; t < k; ++t) ident = ident && kept[j].x[t] == 0 && kept[j].z[t] == 0;
+      if (ident) {  // C^dagger I C = I: no support, no phase
+        P[j].x.assign(n, 0);
+        P[j].z.assign(n, 0);
+        P[j].p = 0;
+        continue;
+      }
+      std::vector<int> xzp(2 * n + 1, 0);
+      for (int t = 0; t < k; ++t) {
+        xzp[s + t] = kept[j].x[t];
+        xzp[n + s + t] = kept[j].z[t];
+      }
+      P[j] = extract_string(xzp.data());
+      GC_CHECK(P[j].l >= 0, GCAMPS_ENUMERIC, "tableau decomposition failed");
+      l = std::min(l, P[j].l);
+      r = std::max(r, P[j].r);
+    }
+    if (r < l) l = r = s;  // U proportional to the identity
+    MpoTerms tm;
+    for (int j = 0; j < J; ++j) {
+      const std::complex<double> cj = kept[j].c * std::polar(1.0, M_PI * P[j].p / d);
+      tm.coef[j] = z64{cj.real(), cj.imag()};
+    }
+    move_centre(l);
+    for (int i = l; i <= r; ++i) {
+      const int kind = (l == r) ? 3 : (i == l ? 0 : (i == r ? 2 : 1));
+      for (int j = 0; j < J; ++j) {
+        tm.x[j] = P[j].x[i];
+        tm.z[j] = P[j].z[i];
+      }
+      launch_mpo_sum_site(stream, kind, d, J, chi[i], chi[i + 1], tm, site[i], spare);
+      std::swap(site[i], spare);
+    }
+    for (int j = l + 1; j <= r; ++j) chi[j] *= J;
+    compress(l, r);
     gates += 1;
     stats[0] += 1;
   }

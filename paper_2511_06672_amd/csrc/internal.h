@@ -85,6 +85,7 @@ void set_error(const std::string& msg);
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 constexpr int kMaxD = 7;
+constexpr int kMaxGateTerms = 81;  // Weyl terms of a general gate (two qutrits: 3^4)
 constexpr int kMaxN = 128;
 constexpr int kSmallEig = 32;   // largest m handled by the single-workgroup eigensolver
 constexpr int kBlk = 16;        // block size of the multi-workgroup block Jacobi

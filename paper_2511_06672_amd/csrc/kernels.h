@@ -55,6 +55,15 @@ struct MpoCoeff {
 // 3 = local operator (l == r).  (dx, dz): exponents of P on this site.
 void launch_mpo_site(hipStream_t s, int kind, int d, int chil, int chir, int dx, int dz,
                      const MpoCoeff& coeff, const z64* in, z64* out);
+// Site update of the MPO sum_j coef_j (x)_i X^{x_ji} Z^{z_ji} of bond J (one term per bond
+// index): kind as above; xz[2j], xz[2j+1] are the exponents of term j on this site; coef is
+// used by kinds 0 and 3 only.
+struct MpoTerms {
+  int x[kMaxGateTerms], z[kMaxGateTerms];
+  z64 coef[kMaxGateTerms];
+};
+void launch_mpo_sum_site(hipStream_t s, int kind, int d, int J, int chil, int chir, const MpoTerms& terms,
+                         const z64* in, z64* out);
 // Theta <- Q_{cstar} Theta in place (no-op when cstar == 0).  Theta (chil, d, d, chir).
 void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* st, const z64* qmats,
                     z64* theta);

@@ -54,6 +54,44 @@ __global__ void k_mpo_site(int kind, int d, int chil, int chir, int dx, int dz, 
   out[idx] = v;
 }
 
+// Site tensor of the MPO sum_j c_j (x)_i X^{x_ji} Z^{z_ji} (bond J, block-diagonal in j):
+//   kind 0 (left end):  out[al, s, (j, be)] = c_j (X^x_j Z^z_j A)[al, s, be]
+//   kind 1 (interior):  out[(j, al), s, (j', be)] = delta_jj' (X^x_j Z^z_j A)[al, s, be]
+//   kind 2 (right end): out[(j, al), s, be] = (X^x_j Z^z_j A)[al, s, be]
+//   kind 3 (one site):  out[al, s, be] = sum_j c_j (X^x_j Z^z_j A)[al, s, be]
+__global__ void k_mpo_sum_site(int kind, int d, int J, int chil, int chir, MpoTerms tm, const z64* __restrict__ in,
+                               z64* __restrict__ out) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ol = (kind == 1 || kind == 2) ? J * chil : chil;
+  const int orr = (kind == 0 || kind == 1) ? J * chir : chir;
+  const size_t total = (size_t)ol * d * orr;
+  if (idx >= total) return;
+  const int col = (int)(idx % orr);
+  const int s = (int)((idx / orr) % d);
+  const int row = (int)(idx / ((size_t)orr * d));
+  auto term = [&](int j, int al, int be) -> z64 {
+    const int a = tm.x[j], c = tm.z[j];
+    const int src = (s - a + d) % d;
+    const double ang = 2.0 * M_PI * (double)((c * src) % d) / (double)d;
+    const z64 v = in[((size_t)al * d + src) * chir + be];
+    return cmul(z64{cos(ang), sin(ang)}, v);
+  };
+  z64 v = {0.0, 0.0};
+  if (kind == 3) {
+    for (int j = 0; j < J; ++j) v = cadd(v, cmul(tm.coef[j], term(j, row, col)));
+  } else if (kind == 0) {
+    const int j = col / chir, be = col % chir;
+    v = cmul(tm.coef[j], term(j, row, be));
+  } else if (kind == 2) {
+    const int j = row / chil, al = row % chil;
+    v = term(j, al, col);
+  } else {
+    const int jl = row / chil, al = row % chil, jr = col / chir, be = col % chir;
+    if (jl == jr) v = term(jl, al, be);
+  }
+  out[idx] = v;
+}
+
 // ===================================================================================== apply Q
 __global__ void k_apply_q(int d, int chil, int chir, const DevStatus* __restrict__ st, const z64* __restrict__ qm,
                           z64* __restrict__ theta) {
@@ -817,6 +855,17 @@ void launch_mpo_site(hipStream_t s, int kind, int d, int chil, int chir, int dx,
   int orr = (kind == 0 || kind == 1) ? d * chir : chir;
   size_t total = (size_t)ol * d * orr;
   hipLaunchKernelGGL(k_mpo_site, dim3(blocks_for(total, 256)), dim3(256), 0, s, kind, d, chil, chir, dx, dz, co, in,
+                     out);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_mpo_sum_site(hipStream_t s, int kind, int d, int J, int chil, int chir, const MpoTerms& terms,
+                         const z64* in, z64* out) {
+  GC_CHECK(J >= 1 && J <= kMaxGateTerms, GCAMPS_EINVAL, "MPO bond out of range");
+  const int ol = (kind == 1 || kind == 2) ? J * chil : chil;
+  const int orr = (kind == 0 || kind == 1) ? J * chir : chir;
+  const size_t total = (size_t)ol * d * orr;
+  hipLaunchKernelGGL(k_mpo_sum_site, dim3(blocks_for(total, 256)), dim3(256), 0, s, kind, d, J, chil, chir, terms, in,
                      out);
   GC_LAUNCH_CHECK();
 }

@@ -24,7 +24,7 @@ WORDS_DISENTANGLERS, WORDS_ALL = 0, 1
 
 SYMBOLS = [
     "gcamps_workspace_bytes", "gcamps_init", "gcamps_destroy", "gcamps_apply_clifford",
-    "gcamps_apply_clifford_layer", "gcamps_apply_phase_rotation", "gcamps_candset_create",
+    "gcamps_apply_clifford_layer", "gcamps_apply_phase_rotation", "gcamps_apply_gate", "gcamps_candset_create",
     "gcamps_candset_destroy", "gcamps_clifford_words", "gcamps_set_candset", "gcamps_score_bond", "gcamps_disentangle", "gcamps_expectation",
     "gcamps_statevector", "gcamps_amplitude", "gcamps_get_tableau", "gcamps_get_bond_dims",
     "gcamps_get_fidelity", "gcamps_get_choice_log", "gcamps_get_site", "gcamps_get_stats",
@@ -43,7 +43,7 @@ class Config(C.Structure):
     _fields_ = [("d", C.c_int32), ("n", C.c_int32), ("chi_max", C.c_int32), ("cutoff", C.c_double),
                 ("score_prec", C.c_int32), ("near_tie", C.c_double), ("tie_tol", C.c_double),
                 ("max_sweeps", C.c_int32), ("auto_disentangle", C.c_int32),
-                ("max_candidates", C.c_int32)]
+                ("max_candidates", C.c_int32), ("max_gate_terms", C.c_int32)]
 
 
 class CWord(C.Structure):
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gcamps_apply_clifford": [P, I32, C.POINTER(CWord)],
         "gcamps_apply_clifford_layer": [P, C.POINTER(I32), C.POINTER(CWord), I32],
         "gcamps_apply_phase_rotation": [P, I32, C.POINTER(D)],
+        "gcamps_apply_gate": [P, I32, I32, C.POINTER(D)],
         "gcamps_candset_create": [I32, C.POINTER(CWord), I32, C.POINTER(P)],
         "gcamps_candset_destroy": [P],
         "gcamps_set_candset": [P, P],
@@ -151,9 +152,9 @@ def _words(words) -> tuple:
 
 
 def make_config(d, n, chi_max, cutoff, score_prec=SCORE_FP64, near_tie=1e-4, tie_tol=1e-10,
-                max_sweeps=2, auto_disentangle=True, max_candidates=512) -> Config:
+                max_sweeps=2, auto_disentangle=True, max_candidates=512, max_gate_terms=0) -> Config:
     return Config(d, n, chi_max, cutoff, score_prec, near_tie, tie_tol, max_sweeps,
-                  1 if auto_disentangle else 0, max_candidates)
+                  1 if auto_disentangle else 0, max_candidates, max_gate_terms)
 
 
 def workspace_bytes(cfg: Config) -> int:
@@ -238,6 +239,14 @@ class State:
     def apply_phase_rotation(self, site: int, phi: Sequence[float]):
         a = (C.c_double * self.d)(*phi)
         _check(lib().gcamps_apply_phase_rotation(self.handle, site, a))
+
+    def apply_gate(self, site: int, u):
+        """General non-Clifford gate (gcamps_apply_gate): u is d^k x d^k (k = 1, 2) acting on
+        sites site..site+k-1, site `site` the most significant digit."""
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.complex128))
+        k = 1 if u.shape[0] == self.d else 2
+        buf = (C.c_double * (2 * u.size))(*u.view(np.float64).reshape(-1))
+        _check(lib().gcamps_apply_gate(self.handle, site, k, buf))
 
     def set_candset(self, cs: CandSet):
         self._candset = cs
