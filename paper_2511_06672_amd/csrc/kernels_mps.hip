@@ -7,6 +7,7 @@
 //  * FP64 selection (lowest index within tie_tol of the minimum) and the low-precision window,
 //  * dense helpers for the validation state vector.
 #include <algorithm>
+#include <type_traits>
 #include <cfloat>
 
 #include "kernels.h"
@@ -334,10 +335,12 @@ __global__ __launch_bounds__(256) void k_gen_rotated(int d_rt, int chil, int chi
 
 // Purity tiles: for candidate slot `ls` of the chunk, tile (I, J), I <= J, of rho = N N^H over the
 // k columns, on MFMA (16x16x4, FP32 or FP64 accumulate).  Each of the four waves owns a quadrant
-// of BL x BL 16x16 blocks (TT = 32 * BL).  The epilogue writes sum |rho_tile|^2 (doubled off the
+// of BL x BL 16x16 blocks (TT = 32 * BL).  The FP32 instance uses three real products per
+// complex product (its three accumulator sets need the whole register file: one workgroup per
+// CU); the FP64 instance (window re-score) uses four and runs two workgroups per CU.  The epilogue writes sum |rho_tile|^2 (doubled off the
 // diagonal) and the tile's trace to partial[slot][tile].
 template <typename T, int BL>
-__global__ __launch_bounds__(256, 2) void k_gram_purity(int m, int k, const cx<T>* __restrict__ nbase, size_t stride,
+__global__ __launch_bounds__(256, (std::is_same<T, float>::value ? 1 : 2)) void k_gram_purity(int m, int k, const cx<T>* __restrict__ nbase, size_t stride,
                                                      int c0, int cnt, const int* __restrict__ nlimit, int ntp,
                                                      double* __restrict__ partial) {
   typedef typename AccT<T>::type acc_t;
@@ -362,12 +365,16 @@ __global__ __launch_bounds__(256, 2) void k_gram_purity(int m, int k, const cx<T
   __shared__ double red[256];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * (TT / 2), wc = (w & 1) * (TT / 2);
-  acc_t accr[BL][BL], acci[BL][BL];
+  // FP32: three real products per complex product, T1 = Ar Br^T, T2 = Ai Bi^T (B holds -Im),
+  // T3 = (Ar + Ai)(Br + Bi)^T; re = T1 - T2, im = T3 - T1 - T2.  FP64: re and im directly.
+  constexpr bool k3 = std::is_same<T, float>::value;
+  acc_t accr[BL][BL], acci[BL][BL], acc3[k3 ? BL : 1][k3 ? BL : 1];
   for (int i = 0; i < BL; ++i)
     for (int j = 0; j < BL; ++j)
       for (int q = 0; q < 4; ++q) {
         accr[i][j][q] = T(0);
         acci[i][j][q] = T(0);
+        if constexpr (k3) acc3[i][j][q] = T(0);
       }
   const int r0 = I * TT, q0 = J * TT;
   constexpr int U = TT * KC / 256;
@@ -414,13 +421,27 @@ __global__ __launch_bounds__(256, 2) void k_gram_purity(int m, int k, const cx<T
         br[i] = Bs[sg][0][ka][wc + i * 16 + (lane & 15)];
         bi[i] = Bs[sg][1][ka][wc + i * 16 + (lane & 15)];
       }
-      for (int i = 0; i < BL; ++i)
-        for (int j = 0; j < BL; ++j) {
-          accr[i][j] = mfma_t(ar[i], br[j], accr[i][j]);
-          accr[i][j] = mfma_t(-ai[i], bi[j], accr[i][j]);
-          acci[i][j] = mfma_t(ar[i], bi[j], acci[i][j]);
-          acci[i][j] = mfma_t(ai[i], br[j], acci[i][j]);
+      if constexpr (k3) {
+        T sa[BL], sb[BL];
+        for (int i = 0; i < BL; ++i) {
+          sa[i] = ar[i] + ai[i];
+          sb[i] = br[i] + bi[i];
         }
+        for (int i = 0; i < BL; ++i)
+          for (int j = 0; j < BL; ++j) {
+            accr[i][j] = mfma_t(ar[i], br[j], accr[i][j]);   // T1
+            acci[i][j] = mfma_t(ai[i], bi[j], acci[i][j]);   // T2
+            acc3[i][j] = mfma_t(sa[i], sb[j], acc3[i][j]);   // T3
+          }
+      } else {
+        for (int i = 0; i < BL; ++i)
+          for (int j = 0; j < BL; ++j) {
+            accr[i][j] = mfma_t(ar[i], br[j], accr[i][j]);
+            accr[i][j] = mfma_t(-ai[i], bi[j], accr[i][j]);
+            acci[i][j] = mfma_t(ar[i], bi[j], acci[i][j]);
+            acci[i][j] = mfma_t(ai[i], br[j], acci[i][j]);
+          }
+      }
     }
     if (more) stash(sg ^ 1);
     __syncthreads();
@@ -434,7 +455,15 @@ __global__ __launch_bounds__(256, 2) void k_gram_purity(int m, int k, const cx<T
         const int row = r0 + wr + i * 16 + mfma_row<T>(lane, q);
         const int col = q0 + wc + j * 16 + (lane & 15);
         if (row < m && col < m) {
-          const double re = (double)accr[i][j][q], im = (double)acci[i][j][q];
+          double re, im;
+          if constexpr (k3) {
+            const double t1 = (double)accr[i][j][q], t2 = (double)acci[i][j][q], t3 = (double)acc3[i][j][q];
+            re = t1 - t2;
+            im = t3 - t1 - t2;
+          } else {
+            re = (double)accr[i][j][q];
+            im = (double)acci[i][j][q];
+          }
           pur += wgt * (re * re + im * im);
           if (I == J && row == col) tr += re;
         }
