@@ -68,6 +68,16 @@ enum {
                               window then decides, as in the FP32 mode. */
 };
 
+/* Disentangler choice at a bond (§3).
+ * RENYI2: the candidate of smallest Renyi-2 entropy (lowest index within tie_tol).
+ * BOND_DIM: the bond-dimension criterion (§4): a candidate is taken only if the bond dimension it
+ *   leaves (the truncation rule of the split applied to the singular values of the rotated
+ *   two-site tensor) is below the identity's; among the candidates of the smallest bond
+ *   dimension the smallest Renyi-2 entropy wins (lowest index within tie_tol).  Needs
+ *   GCAMPS_SCORE_FP64; two-site matrices whose smaller side exceeds 32 or with more than 8192
+ *   entries give EUNSUPPORTED. */
+enum { GCAMPS_CRITERION_RENYI2 = 0, GCAMPS_CRITERION_BOND_DIM = 1 };
+
 typedef struct gcamps_ctx gcamps_ctx;
 typedef struct gcamps_candset gcamps_candset;
 
@@ -85,6 +95,7 @@ typedef struct {
   int32_t max_gate_terms;   /* largest number of Weyl terms of a gcamps_apply_gate unitary (its MPO
                                bond, 1..81); 0 means d (diagonal phase gates only).  Bond
                                capacity is chi_max * max(d, max_gate_terms) <= 4096. */
+  int32_t criterion;        /* GCAMPS_CRITERION_*: how a disentangler is chosen at a bond */
 } gcamps_config;
 
 /* A two-qudit Clifford word on the ordered pair (a, b) = (site, site + 1):

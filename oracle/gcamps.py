@@ -37,7 +37,8 @@ from typing import List, Sequence, Tuple
 import numpy as np
 
 from .clifford import word_matrix
-from .mps import MPS
+from .mps import MPS, rtrunc
+from .mps import svd as mps_svd
 from .tableau import Tableau
 from .weyl import Weyl, omega, site_matrix, tau
 
@@ -96,6 +97,7 @@ class Config:
     tie_tol: float = 1e-10
     max_sweeps: int = 2
     auto_disentangle: bool = True
+    criterion: str = "renyi2"   # or "bond_dim": the bond-dimension criterion (§4)
 
 
 @dataclass
@@ -206,6 +208,28 @@ class Gcamps:
         lim = np.min(s2) + self.cfg.tie_tol
         return int(np.nonzero(s2 <= lim)[0][0])
 
+    def ranks(self, theta: np.ndarray) -> np.ndarray:
+        """Bond dimension each candidate leaves: the split's truncation rule applied to the
+        singular values of the rotated two-site tensor."""
+        cl, d, _, cr = theta.shape
+        out = np.empty(len(self._cand_mats), dtype=np.int64)
+        for c, q in enumerate(self._cand_mats):
+            m = np.einsum("xy,ayb->axb", q, theta.reshape(cl, d * d, cr)).reshape(cl * d, d * cr)
+            _, s, _ = mps_svd(m)
+            out[c] = rtrunc(s, self.cfg.cutoff, self.cfg.chi_max)[0]
+        return out
+
+    def select_bond_dim(self, theta: np.ndarray) -> int:
+        """Bond-dimension criterion: keep the identity unless a candidate leaves a smaller bond
+        dimension; among the candidates of the smallest one, the rule of `select` on their S2."""
+        r = self.ranks(theta)
+        if r.min() >= r[0]:
+            return 0
+        s2 = self.scores(theta)
+        best = np.nonzero(r == r.min())[0]
+        lim = np.min(s2[best]) + self.cfg.tie_tol
+        return int(best[np.nonzero(s2[best] <= lim)[0][0]])
+
     def disentangle(self) -> Tuple[int, int]:
         """Sweeps of the disentangler; returns (sweeps run, bonds changed)."""
         n = self.n
@@ -220,6 +244,8 @@ class Gcamps:
                 th = self.mps.theta(i)
                 if self._frozen_choices is not None:
                     c = self._frozen_choices.pop(0)
+                elif self.cfg.criterion == "bond_dim":
+                    c = self.select_bond_dim(th)
                 else:
                     c = self.select(self.scores(th))
                 self.choice_log.append(ChoiceEntry(self.gate_count - 1, sweep, i, c))

@@ -40,6 +40,10 @@ void validate_config(const gcamps_config* c) {
   GC_CHECK(c->d >= 2 && c->d <= kMaxD, GCAMPS_EINVAL, "d out of range [2, 7]");
   GC_CHECK(is_prime(c->d), GCAMPS_EUNSUPPORTED, "d must be prime (decomposition over the field Z_d)");
   GC_CHECK(c->n >= 2 && c->n <= kMaxN, GCAMPS_EINVAL, "n out of range [2, 128]");
+  GC_CHECK(c->criterion == GCAMPS_CRITERION_RENYI2 || c->criterion == GCAMPS_CRITERION_BOND_DIM, GCAMPS_EINVAL,
+           "criterion must be GCAMPS_CRITERION_RENYI2 or _BOND_DIM");
+  GC_CHECK(c->criterion != GCAMPS_CRITERION_BOND_DIM || c->score_prec == GCAMPS_SCORE_FP64, GCAMPS_EINVAL,
+           "the bond-dimension criterion uses FP64 scores (score_prec = GCAMPS_SCORE_FP64)");
   GC_CHECK(c->max_gate_terms >= 0 && c->max_gate_terms <= kMaxGateTerms, GCAMPS_EINVAL,
            "max_gate_terms out of range [0, 81]");
   GC_CHECK(c->chi_max >= 1 && (size_t)c->chi_max * std::max(c->d, c->max_gate_terms) <= 4096, GCAMPS_EINVAL,
@@ -174,7 +178,10 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
     Layout lay = make_layout(*cfg);
     GC_CHECK(bytes >= lay.total, GCAMPS_EWORKSPACE, "workspace smaller than gcamps_workspace_bytes()");
     static std::once_flag attrs_once;
-    std::call_once(attrs_once, linalg_set_attributes);
+    std::call_once(attrs_once, [] {
+      linalg_set_attributes();
+      rank_set_attributes();
+    });
     auto c = std::make_unique<gcamps_ctx>();
     c->cfg = *cfg;
     c->lay = lay;

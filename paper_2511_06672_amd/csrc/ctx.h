@@ -505,6 +505,14 @@ struct gcamps_ctx {
     int sweeps = 0, changed_total = 0;
     const int prec = cfg.score_prec;
     const bool frozen = choice_frz != nullptr;
+    if (cfg.criterion == GCAMPS_CRITERION_BOND_DIM && !frozen) {
+      // checked before any change: under this criterion no bond grows during the sweeps
+      for (int i = 0; i + 1 < n; ++i) {
+        const int mm = std::min(chi[i] * d, d * chi[i + 2]), kk = std::max(chi[i] * d, d * chi[i + 2]);
+        GC_CHECK(mm <= kRankMaxM && (size_t)(mm + (mm & 1)) * kk <= kRankMaxElems, GCAMPS_EUNSUPPORTED,
+                 "bond-dimension criterion: two-site matrix too large (smaller side <= 32, at most 8192 entries)");
+      }
+    }
     for (int sw = 0; sw < cfg.max_sweeps; ++sw) {
       ++sweeps;
       const bool ltr = (sw % 2 == 0);
@@ -539,7 +547,10 @@ struct gcamps_ctx {
           launch_score(stream, prec, d, cl, cr, theta, q64, q32, nullptr, ncand, nullptr, s2, partial, pcap, nbuf,
                        lay.nbuf_bytes, gram_ev.data(), (int)gram_ev.size(), &gram_used, rtab);
           GC_HIP(hipEventRecord(ev1, stream));
-          if (prec == GCAMPS_SCORE_FP64) {
+          if (cfg.criterion == GCAMPS_CRITERION_BOND_DIM) {
+            launch_cand_rank(stream, d, cl, cr, theta, q64, ncand, cfg.cutoff, cfg.chi_max, wlist);
+            launch_select_rank(stream, ncand, wlist, s2, cfg.tie_tol, st);
+          } else if (prec == GCAMPS_SCORE_FP64) {
             launch_select(stream, ncand, s2, cfg.tie_tol, st);
           } else {
             launch_window(stream, ncand, s2, cfg.near_tie, wlist, st);

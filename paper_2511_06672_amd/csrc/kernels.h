@@ -81,6 +81,19 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
                   const z64* replica_tables = nullptr);
 void launch_select(hipStream_t s, int count, const double* s2, double tie_tol, DevStatus* st);
 
+// ------------------------------------------------------------------ bond-dimension criterion (kernels_rank.hip)
+constexpr int kRankMaxM = 32;        // smaller side of the two-site matrix
+constexpr int kRankMaxElems = 8192;  // entries of the two-site matrix (LDS of one workgroup)
+// rank_out[c] = bond dimension left by candidate c (truncation rule of the split applied to the
+// singular values of reshape(Q_c Theta), one-sided Jacobi SVD per candidate).
+void launch_cand_rank(hipStream_t s, int d, int chil, int chir, const z64* theta, const z64* qmats, int count,
+                      double cutoff, int chi_max, int* rank_out);
+// c* = 0 unless some candidate's rank is below the identity's; then the lowest index of the
+// smallest rank with s2 <= min s2 (over that rank) + tie_tol.
+void launch_select_rank(hipStream_t s, int count, const int* rank, const double* s2, double tie_tol,
+                        DevStatus* st);
+void rank_set_attributes();
+
 // ------------------------------------------------------------------ replica scoring (kernels_replica.hip)
 // Full-set scores through the replica tensor of Theta (d = 2, 3): the Gram F of Theta over its
 // larger bond, the pair sum A, and one D^4 dot product per candidate with its table.

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EWORKSPACE", -4:
                 -5: "EDEVICE", -6: "ENUMERIC"}
 SCORE_FP64, SCORE_FP32, SCORE_BF16, SCORE_REPLICA = 0, 1, 2, 3
 WORDS_DISENTANGLERS, WORDS_ALL = 0, 1
+CRITERION_RENYI2, CRITERION_BOND_DIM = 0, 1
 
 SYMBOLS = [
     "gcamps_workspace_bytes", "gcamps_init", "gcamps_destroy", "gcamps_apply_clifford",
@@ -43,7 +44,7 @@ class Config(C.Structure):
     _fields_ = [("d", C.c_int32), ("n", C.c_int32), ("chi_max", C.c_int32), ("cutoff", C.c_double),
                 ("score_prec", C.c_int32), ("near_tie", C.c_double), ("tie_tol", C.c_double),
                 ("max_sweeps", C.c_int32), ("auto_disentangle", C.c_int32),
-                ("max_candidates", C.c_int32), ("max_gate_terms", C.c_int32)]
+                ("max_candidates", C.c_int32), ("max_gate_terms", C.c_int32), ("criterion", C.c_int32)]
 
 
 class CWord(C.Structure):
@@ -152,9 +153,10 @@ def _words(words) -> tuple:
 
 
 def make_config(d, n, chi_max, cutoff, score_prec=SCORE_FP64, near_tie=1e-4, tie_tol=1e-10,
-                max_sweeps=2, auto_disentangle=True, max_candidates=512, max_gate_terms=0) -> Config:
+                max_sweeps=2, auto_disentangle=True, max_candidates=512, max_gate_terms=0,
+                criterion=0) -> Config:
     return Config(d, n, chi_max, cutoff, score_prec, near_tie, tie_tol, max_sweeps,
-                  1 if auto_disentangle else 0, max_candidates, max_gate_terms)
+                  1 if auto_disentangle else 0, max_candidates, max_gate_terms, criterion)
 
 
 def workspace_bytes(cfg: Config) -> int:

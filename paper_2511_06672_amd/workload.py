@@ -177,6 +177,21 @@ def brickwork_circuit(d: int, n: int, layers: int, n_phase: int, seed: int,
     return Circuit(d, n, out)
 
 
+def paper_circuit(d: int, n: int, layers: int, seed: int, depth: int | None = None) -> Circuit:
+    """The paper's benchmark circuit (Fig. 3 of §4): each layer is a random Clifford followed by
+    one T gate on the first qudit.  The random Clifford is `depth` (default n) brickwork
+    sublayers of random two-qudit words, a deep random Clifford circuit standing in for a draw
+    from the whole n-qudit Clifford group; the T gate follows the layer's last sublayer."""
+    depth = n if depth is None else depth
+    rc = substream(seed, STREAM_CIRCUIT)
+    out: List[Layer] = []
+    for _ in range(layers):
+        for s in range(depth):
+            out.append(Layer([Brick(site, random_word(rc, d)) for site in brick_sites(n, s)]))
+        out[-1].phases.append(PhaseGate(0, t_gate_phases(d)))
+    return Circuit(d, n, out)
+
+
 def candidate_words(d: int, count: int, seed: int, ngens: int = 30) -> List[Word]:
     """Candidate disentanglers: index 0 is the identity, the rest seeded random words."""
     rng = substream(seed, STREAM_CANDIDATES)
@@ -199,7 +214,8 @@ class Workload:
     cutoff: float
     max_sweeps: int = 2
     # "listed": `candidates` is the set; "all_sp4": every two-qudit Clifford up to Weyl shifts
-    # (720 for qubits), enumerated by the caller (this module holds no Clifford arithmetic)
+    # (720 for qubits); "exhaustive": the unique disentanglers (20 / 90); the last two are
+    # enumerated by the caller (this module holds no Clifford arithmetic)
     candidate_set: str = "listed"
 
 
@@ -223,6 +239,15 @@ def workload(name: str, n: int | None = None) -> Workload:
         c = brickwork_circuit(3, nn, 2 * nn, 32, seed, one_per_layer=False,
                               parametrised=True)
         return Workload(name, c, candidate_words(3, 512, seed), chi_max=256, cutoff=1e-10)
+    if name in ("paper_d3_n12", "paper_d2_n12"):
+        # the paper's own workload: N = 12 qudits, N layers of (random Clifford, T on qudit 0),
+        # no truncation beyond the rank floor; disentangled with the exhaustive set under the
+        # bond-dimension criterion (the caller supplies the set: gcamps_clifford_words)
+        dd = 3 if name == "paper_d3_n12" else 2
+        nn = 12 if n is None else n
+        seed = 6000 + dd
+        c = paper_circuit(dd, nn, nn, seed)
+        return Workload(name, c, [], chi_max=dd ** (nn // 2), cutoff=0.0, candidate_set="exhaustive")
     if name == "mixed_d2_n64":
         # mixed run, qubit part: one T = diag(1, e^{i pi/4}) per layer, chi_max 1024, cutoff
         # 1e-12, the 720 elements of Sp(4, Z_2) as candidates

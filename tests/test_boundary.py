@@ -52,6 +52,15 @@ def test_replica_mode_sizing_and_validation():
     assert e.value.code == -2
 
 
+def test_criterion_validation():
+    assert g.workspace_bytes(g.make_config(3, 8, 27, 0.0, criterion=g.CRITERION_BOND_DIM)) > 0
+    for bad in (g.make_config(3, 8, 27, 0.0, criterion=2),
+                g.make_config(3, 8, 27, 0.0, score_prec=g.SCORE_REPLICA, criterion=g.CRITERION_BOND_DIM)):
+        with pytest.raises(g.GcampsError) as e:
+            g.workspace_bytes(bad)
+        assert e.value.code == -1
+
+
 def test_candset_validation():
     cs = g.CandSet(3, candidate_words(3, 8, 3))
     assert cs.count == 8
