@@ -32,6 +32,12 @@ angles (qutrits, n = 24, 48 layers, 32 parametrised gates, chi_max = 256, cutoff
 
     python bench.py --workload grad
 
+A fourth runs the paper's own circuits (random Clifford layers, T on qudit 0; qutrits and
+qubits at N = 12 and 16, N layers) with the exhaustive disentanglers under the bond-dimension
+criterion, reporting the rate and the largest bond after each layer:
+
+    python bench.py --workload paper
+
 A plain device copy of known size calibrates the HBM counters (FETCH_SIZE, WRITE_SIZE)
 used for the roofline's traffic figure:
 
@@ -310,6 +316,87 @@ def main_grad(args):
     print(json.dumps(out), flush=True)
 
 
+def run_paper(g, name, n):
+    """One paper-workload circuit on the GPU with the bond-dimension criterion and the
+    exhaustive disentangler set; returns (seconds, gates, max bond after each T gate)."""
+    import torch
+    from paper_2511_06672_amd.workload import workload
+    wl = workload(name, n=n)
+    c = wl.circuit
+    words = g.clifford_words(c.d, g.WORDS_DISENTANGLERS)
+    st = g.State(g.make_config(c.d, c.n, wl.chi_max, wl.cutoff, criterion=g.CRITERION_BOND_DIM,
+                               max_candidates=len(words)))
+    st.set_candset(g.CandSet(c.d, words))
+    dims = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for layer in c.layers:
+        if layer.bricks:
+            st.apply_clifford_layer([b.site for b in layer.bricks], [b.word for b in layer.bricks])
+        for ph in layer.phases:
+            st.apply_phase_rotation(ph.site, ph.phi)
+            dims.append(int(max(st.bond_dims())))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, c.n_phase_gates, dims
+
+
+def paper_cpu_baseline(runs):
+    """The oracle on the N = 12 paper circuits (same criterion and sets)."""
+    import os
+    from oracle.disentanglers import exhaustive_disentanglers
+    from oracle.gcamps import Config, Gcamps
+    from paper_2511_06672_amd.workload import Word, workload
+    gates, secs = 0, 0.0
+    for name, n in runs:
+        wl = workload(name, n=n)
+        c = wl.circuit
+        words = [Word(w, (0, 0, 0, 0)) for w in exhaustive_disentanglers(c.d)]
+        t0 = time.perf_counter()
+        orc = Gcamps(c.d, c.n, Config(chi_max=wl.chi_max, cutoff=wl.cutoff, criterion="bond_dim"), words)
+        for layer in c.layers:
+            for b in layer.bricks:
+                orc.apply_clifford(b.site, b.word.gens, b.word.weyl)
+            for ph in layer.phases:
+                orc.apply_phase_rotation(ph.site, ph.phi)
+        secs += time.perf_counter() - t0
+        gates += c.n_phase_gates
+    return {"value": gates / secs, "unit": "non-Clifford gates/s", "cores": os.cpu_count() or 1,
+            "kind": "oracle", "sample": f"{', '.join(f'{a} n={b}' for a, b in runs)} in full "
+                                        f"({gates} gates, {secs:.1f} s)"}
+
+
+def main_paper(args):
+    """The paper's own workload (random Clifford layers, T on qudit 0) with the bond-dimension
+    criterion: qutrits and qubits at N = 12 and 16, N layers each (up to the transition, where
+    the bond dimension starts to grow)."""
+    import torch
+    from paper_2511_06672_amd import gcamps as g
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    runs = [("paper_d3_n12", 12), ("paper_d2_n12", 12), ("paper_d3_n12", 16), ("paper_d2_n12", 16)]
+    for w in range(args.warmup):
+        log(f"warmup {w + 1}/{args.warmup}")
+        run_paper(g, "paper_d3_n12", 8)
+    per, gates, secs = {}, 0, 0.0
+    for name, n in runs:
+        t, ng, dims = run_paper(g, name, n)
+        log(f"{name} n={n}: {ng} T gates in {t:.2f} s, max bond per layer {dims}")
+        per[f"{name[:8]}_n{n}"] = {"seconds": t, "gates": ng, "gates_per_s": ng / t, "max_bond_per_layer": dims}
+        gates += ng
+        secs += t
+    cpu = None if args.no_cpu else paper_cpu_baseline(runs[:2])
+    out = {
+        "metric": "non-Clifford gates/sec, paper workload with the bond-dimension criterion",
+        "value": gates / secs, "unit": "non-Clifford gates/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+        "ms_per_step": 1e3 * secs, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128", "data": "synthetic (seeded random Clifford layers, T on qudit 0)",
+        "config": {"workload": "paper circuits: N in {12, 16}, N layers of (random Clifford, T on qudit 0), "
+                               "d in {2, 3}, exhaustive disentanglers, bond-dimension criterion, no truncation",
+                   "parallelism": "1 GPU"},
+        "runs": per, "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main_copy(args):
     """Plain device-to-device copies of a known size (counter calibration)."""
     import torch
@@ -336,7 +423,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["headline", "batch", "grad", "copy"], default="headline")
+    ap.add_argument("--workload", choices=["headline", "batch", "grad", "paper", "copy"], default="headline")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--serial-check", action="store_true", help="batch: also run on one lane")
@@ -360,6 +447,9 @@ def main():
         return
     if args.workload == "copy":
         main_copy(args)
+        return
+    if args.workload == "paper":
+        main_paper(args)
         return
 
     import numpy as np

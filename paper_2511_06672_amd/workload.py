@@ -247,7 +247,7 @@ def workload(name: str, n: int | None = None) -> Workload:
         nn = 12 if n is None else n
         seed = 6000 + dd
         c = paper_circuit(dd, nn, nn, seed)
-        return Workload(name, c, [], chi_max=dd ** (nn // 2), cutoff=0.0, candidate_set="exhaustive")
+        return Workload(name, c, [], chi_max=min(dd ** (nn // 2), 1024), cutoff=0.0, candidate_set="exhaustive")
     if name == "mixed_d2_n64":
         # mixed run, qubit part: one T = diag(1, e^{i pi/4}) per layer, chi_max 1024, cutoff
         # 1e-12, the 720 elements of Sp(4, Z_2) as candidates
