@@ -186,10 +186,18 @@ def main_batch(args):
         log(f"warmup {w + 1}/{args.warmup} (first 4 circuits)")
         g.batch_run(bw.circuits[:4], cfgs[:4], cs, lanes=min(4, args.lanes))
     times, st = [], None
+    chunk = args.batch_chunk or len(bw.circuits)
     for k in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res, st = g.batch_run(bw.circuits, cfgs, cs, lanes=args.lanes)
+        res, st = [], {}
+        for i0 in range(0, len(bw.circuits), chunk):  # chunks only to report progress
+            r, s = g.batch_run(bw.circuits[i0:i0 + chunk], cfgs[i0:i0 + chunk], cs, lanes=args.lanes)
+            res += r
+            for key, v in s.items():
+                st[key] = v if key == "lanes" else st.get(key, 0) + v
+            if chunk < len(bw.circuits):
+                log(f"  {len(res)}/{len(bw.circuits)} circuits done, {time.perf_counter() - t0:.1f} s")
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         log(f"timed step {k + 1}/{args.steps}: {times[-1]:.2f} s ({st['gates'] / times[-1]:.2f} gates/s)")
@@ -426,6 +434,8 @@ def main():
     ap.add_argument("--workload", choices=["headline", "batch", "grad", "paper", "copy"], default="headline")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--batch-chunk", type=int, default=0,
+                    help="batch: run the circuits in chunks of this many (progress lines; 0 = all at once)")
     ap.add_argument("--serial-check", action="store_true", help="batch: also run on one lane")
     ap.add_argument("--score", choices=["fp32", "bf16"], default="fp32",
                     help="headline: precision of the timed path's candidate scoring")

@@ -365,7 +365,10 @@ __global__ __launch_bounds__(256) void k_jacobi_small(const z64* __restrict__ G,
     cur ^= res;
     ++sweeps;
     __syncthreads();
-    if (!any) {
+    // every wave reads the flag before thread 0 resets it for the next sweep
+    const int rotated = any;
+    __syncthreads();
+    if (!rotated) {
       conv = true;
       break;
     }

@@ -107,3 +107,23 @@ def test_batch_without_candidates_only_compresses():
     assert stats["bonds"] == 0
     for r in res:
         assert r["status"] == 0 and r["choices_len"] == 0
+
+
+def test_many_lanes_on_the_batch_workload():
+    """32 circuits of the batch workload on 8 concurrent lanes: every circuit completes, and two
+    of them equal their single-state runs bit for bit.  (Concurrent lanes slow some waves of a
+    workgroup relative to others; the single-workgroup eigensolver once read its convergence
+    flag after the next sweep had reset it, which only showed up under such load.)"""
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import batch_workload
+    print("[gpu-case] batch workload, 32 circuits on 8 lanes", flush=True)
+    bw = batch_workload(count=32)
+    cfgs = [g.make_config(3, c.n, bw.chi_max, bw.cutoff, score_prec=g.SCORE_FP32, near_tie=1e-4,
+                          max_sweeps=bw.max_sweeps, max_candidates=len(bw.candidates)) for c in bw.circuits]
+    cs = g.CandSet(3, bw.candidates)
+    res, stats = g.batch_run(bw.circuits, cfgs, cs, lanes=8)
+    assert all(r["status"] == 0 for r in res) and stats["circuits"] == 32
+    for i in (0, 19):
+        st, _ = single_state(g, bw.circuits[i], cfgs[i], cs)
+        assert res[i]["fidelity"] == st.fidelity()
+        assert res[i]["bond_dims"] == st.bond_dims()
