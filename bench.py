@@ -405,6 +405,98 @@ def main_paper(args):
     print(json.dumps(out), flush=True)
 
 
+def run_general(g, name, prec, n=None):
+    """One general-gate workload circuit on the GPU (Haar-random one- or two-site unitaries
+    after each brickwork layer, applied through gcamps_apply_gate); returns (state, seconds,
+    candidate count, gate count)."""
+    import torch
+    from paper_2511_06672_amd.workload import workload
+    wl = workload(name, n=n)
+    c = wl.circuit
+    cands = g.clifford_words(c.d, g.WORDS_ALL) if wl.candidate_set == "all_sp4" else wl.candidates
+    k = max(gg.k for L in c.layers for gg in L.gates)
+    cfg = g.make_config(c.d, c.n, wl.chi_max, wl.cutoff, score_prec=prec, near_tie=NEAR_TIE,
+                        max_sweeps=wl.max_sweeps, max_candidates=len(cands), max_gate_terms=c.d ** (2 * k))
+    st = g.State(cfg)
+    st.set_candset(g.CandSet(c.d, cands))
+    mats = [[np.array(gg.u, dtype=np.complex128).reshape(c.d ** gg.k, c.d ** gg.k) for gg in L.gates]
+            for L in c.layers]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for L, us in zip(c.layers, mats):
+        if L.bricks:
+            st.apply_clifford_layer([b.site for b in L.bricks], [b.word for b in L.bricks])
+        for gg, u in zip(L.gates, us):
+            st.apply_gate(gg.site, u)
+    torch.cuda.synchronize()
+    return st, time.perf_counter() - t0, len(cands), c.n_general_gates
+
+
+def general_cpu_baseline(name, budget_s):
+    """The oracle on the same general-gate circuit, gate by gate, until the budget is spent."""
+    import os
+    from oracle.disentanglers import all_cliffords
+    from oracle.gcamps import Config, Gcamps
+    from paper_2511_06672_amd.workload import Word, workload
+    wl = workload(name)
+    c = wl.circuit
+    cands = ([Word(w, (0, 0, 0, 0)) for w, _ in all_cliffords(c.d)] if wl.candidate_set == "all_sp4"
+             else wl.candidates)
+    orc = Gcamps(c.d, c.n, Config(chi_max=wl.chi_max, cutoff=wl.cutoff, max_sweeps=wl.max_sweeps), cands)
+    t0 = time.perf_counter()
+    done = 0
+    for L in c.layers:
+        if time.perf_counter() - t0 > budget_s:
+            break
+        for b in L.bricks:
+            orc.apply_clifford(b.site, b.word.gens, b.word.weyl)
+        for gg in L.gates:
+            orc.apply_gate(gg.site, np.array(gg.u, dtype=complex).reshape(c.d ** gg.k, c.d ** gg.k))
+            done += 1
+    secs = time.perf_counter() - t0
+    return {"value": done / secs, "unit": "non-Clifford gates/s", "cores": os.cpu_count() or 1,
+            "kind": "oracle", "sample": f"first {done} of {c.n_general_gates} gates of {name} "
+                                        f"(max bond {max(orc.mps.bond_dims())}, {secs:.1f} s)"}
+
+
+def main_gates(args):
+    """General non-Clifford gates: a Haar-random single-qutrit unitary (up to 9 Weyl terms)
+    after each brickwork layer of a 24-qutrit chain, and a Haar-random two-qubit unitary (up to
+    16 terms) after each layer of a 24-qubit chain; chi_max 64, FP32 scoring with the FP64
+    near-tie window."""
+    import torch
+    from paper_2511_06672_amd import gcamps as g
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    names = ["general_d3_n24", "general_d2_n24"]
+    for w in range(args.warmup):
+        log(f"warmup {w + 1}/{args.warmup} (n = 8 copies)")
+        for name in names:
+            run_general(g, name, g.SCORE_FP32, n=8)
+    per, gates, secs = {}, 0, 0.0
+    for name in names:
+        st, t, ncand, ng = run_general(g, name, g.SCORE_FP32)
+        log(f"{name}: {ng} gates in {t:.2f} s, F_est {st.fidelity():.6f}, max bond {max(st.bond_dims())}")
+        per[name] = {"seconds": t, "gates": ng, "gates_per_s": ng / t, "candidates": ncand,
+                     "fidelity": st.fidelity(), "final_bond_dim_max": int(max(st.bond_dims())),
+                     "choices": int(len(st.choice_log()))}
+        gates += ng
+        secs += t
+    cpu = None if args.no_cpu else general_cpu_baseline(names[0], args.cpu_budget)
+    out = {
+        "metric": "general non-Clifford gates/sec incl. disentangling",
+        "value": gates / secs, "unit": "non-Clifford gates/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+        "ms_per_step": 1e3 * secs, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 scoring / c128 commit",
+        "data": "synthetic (seeded brickwork circuits, Haar-random gates and candidate sets)",
+        "config": {"workload": "general gates: qutrits n=24, 24 layers, a Haar-random one-qutrit U per layer, "
+                               "512 candidates; qubits n=24, 24 layers, a Haar-random two-qubit U per layer, "
+                               "720 candidates; chi_max=64, cutoff=1e-10",
+                   "parallelism": "1 GPU", "near_tie": NEAR_TIE},
+        "runs": per, "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main_copy(args):
     """Plain device-to-device copies of a known size (counter calibration)."""
     import torch
@@ -431,7 +523,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["headline", "batch", "grad", "paper", "copy"], default="headline")
+    ap.add_argument("--workload", choices=["headline", "batch", "grad", "paper", "gates", "copy"], default="headline")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--batch-chunk", type=int, default=0,
@@ -457,6 +549,9 @@ def main():
         return
     if args.workload == "copy":
         main_copy(args)
+        return
+    if args.workload == "gates":
+        main_gates(args)
         return
     if args.workload == "paper":
         main_paper(args)

@@ -321,7 +321,7 @@ def apply_dense_two_site(v: np.ndarray, d: int, n: int, site: int, u: np.ndarray
 
 def run_circuit(circuit, candidates, cfg: Config, record_states: bool = False,
                 phases_override=None, frozen=None) -> Gcamps:
-    """Run a workload circuit (bricks then phase gates, layer by layer).
+    """Run a workload circuit (bricks, then phase gates, then general gates, layer by layer).
     ``phases_override[param]`` replaces the angles of parametrised gates."""
     g = Gcamps(circuit.d, circuit.n, cfg, candidates, frozen=frozen)
     for layer in circuit.layers:
@@ -332,4 +332,7 @@ def run_circuit(circuit, candidates, cfg: Config, record_states: bool = False,
             if phases_override is not None and ph.param >= 0:
                 phi = phases_override[ph.param]
             g.apply_phase_rotation(ph.site, phi)
+        for gg in layer.gates:
+            D = circuit.d ** gg.k
+            g.apply_gate(gg.site, np.array(gg.u, dtype=complex).reshape(D, D))
     return g

@@ -337,7 +337,8 @@ class State:
 
 
 def run_circuit(state: State, circuit, phases_override=None):
-    """Apply a workload circuit layer by layer (bricks as one layer launch, then phases)."""
+    """Apply a workload circuit layer by layer (bricks as one layer launch, then phases, then
+    general gates)."""
     for layer in circuit.layers:
         if layer.bricks:
             state.apply_clifford_layer([b.site for b in layer.bricks], [b.word for b in layer.bricks])
@@ -346,6 +347,9 @@ def run_circuit(state: State, circuit, phases_override=None):
             if phases_override is not None and ph.param >= 0:
                 phi = phases_override[ph.param]
             state.apply_phase_rotation(ph.site, phi)
+        for gg in layer.gates:
+            D = state.d ** gg.k
+            state.apply_gate(gg.site, np.array(gg.u, dtype=np.complex128).reshape(D, D))
     return state
 
 
@@ -354,6 +358,9 @@ def _circuit_ops(circuit, keep: list, phases_override=None):
     ops = []
     params = []
     for layer in circuit.layers:
+        if layer.gates:
+            raise GcampsError(-2, "batched circuits carry Clifford layers and phase gates only; "
+                                  "apply general gates through State.apply_gate")
         if layer.bricks:
             arr, kw = _words([b.word for b in layer.bricks])
             sites = (C.c_int32 * len(layer.bricks))(*[b.site for b in layer.bricks])

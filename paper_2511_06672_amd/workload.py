@@ -45,6 +45,7 @@ STREAM_PHASE_POS = 2
 STREAM_CANDIDATES = 3
 STREAM_THETA = 4
 STREAM_BATCH = 5
+STREAM_GATES = 6
 
 
 class SplitMix64:
@@ -98,9 +99,17 @@ class PhaseGate:
 
 
 @dataclass
+class GeneralGate:
+    site: int                  # acts on sites site .. site + k - 1 (site the most significant digit)
+    k: int
+    u: Tuple[complex, ...]     # the d^k x d^k unitary, row-major
+
+
+@dataclass
 class Layer:
     bricks: List[Brick] = field(default_factory=list)
     phases: List[PhaseGate] = field(default_factory=list)
+    gates: List[GeneralGate] = field(default_factory=list)   # applied after the phases
 
 
 @dataclass
@@ -112,6 +121,10 @@ class Circuit:
     @property
     def n_phase_gates(self) -> int:
         return sum(len(L.phases) for L in self.layers)
+
+    @property
+    def n_general_gates(self) -> int:
+        return sum(len(L.gates) for L in self.layers)
 
 
 def t_gate_phases(d: int) -> Tuple[float, ...]:
@@ -192,6 +205,46 @@ def paper_circuit(d: int, n: int, layers: int, seed: int, depth: int | None = No
     return Circuit(d, n, out)
 
 
+def haar_unitary(rng: SplitMix64, D: int) -> Tuple[complex, ...]:
+    """Haar-random D x D unitary, row-major: the columns of a matrix of standard complex
+    Gaussians (Box-Muller on the stream's uniforms, drawn row by row) orthonormalised by
+    modified Gram-Schmidt, which is QR with a positive diagonal in R, so the result is Haar
+    distributed (Mezzadri, "How to generate random matrices from the classical compact groups",
+    2007).  Plain Python arithmetic, so every machine draws the same matrix."""
+    z = [[0j] * D for _ in range(D)]
+    for i in range(D):
+        for j in range(D):
+            u1 = 1.0 - rng.uniform()          # (0, 1]
+            u2 = rng.uniform()
+            rad = math.sqrt(-math.log(u1))    # |z|^2 ~ Exp(1): unit variance complex
+            z[i][j] = complex(rad * math.cos(2 * math.pi * u2), rad * math.sin(2 * math.pi * u2))
+    cols = [[z[i][j] for i in range(D)] for j in range(D)]
+    for j in range(D):
+        v = cols[j]
+        for q in cols[:j]:
+            ov = sum(a.conjugate() * b for a, b in zip(q, v))
+            v = [b - ov * a for a, b in zip(q, v)]
+        nrm = math.sqrt(sum(abs(b) ** 2 for b in v))
+        cols[j] = [b / nrm for b in v]
+    return tuple(cols[j][i] for i in range(D) for j in range(D))
+
+
+def general_circuit(d: int, n: int, layers: int, k: int, seed: int, ngens: int = 30) -> Circuit:
+    """Brickwork Clifford layers (the word stream of ``brickwork_circuit``), each followed by one
+    Haar-random k-qudit unitary (k = 1, 2) on sites (s, .., s + k - 1), s uniform in
+    0 .. n - k: general non-diagonal non-Clifford gates, expanded on the d^(2k) Weyl operators."""
+    rc = substream(seed, STREAM_CIRCUIT)
+    rp = substream(seed, STREAM_PHASE_POS)
+    ru = substream(seed, STREAM_GATES)
+    out = [Layer() for _ in range(layers)]
+    for L in range(layers):
+        for s in brick_sites(n, L):
+            out[L].bricks.append(Brick(s, random_word(rc, d, ngens)))
+        site = rp.below(n - k + 1)
+        out[L].gates.append(GeneralGate(site, k, haar_unitary(ru, d ** k)))
+    return Circuit(d, n, out)
+
+
 def candidate_words(d: int, count: int, seed: int, ngens: int = 30) -> List[Word]:
     """Candidate disentanglers: index 0 is the identity, the rest seeded random words."""
     rng = substream(seed, STREAM_CANDIDATES)
@@ -264,6 +317,21 @@ def workload(name: str, n: int | None = None) -> Workload:
         layers = 60 if n is None else max(8, (60 * nn) // 48)
         c = brickwork_circuit(3, nn, layers, layers, seed)
         return Workload(name, c, candidate_words(3, 720, seed), chi_max=1024, cutoff=1e-12)
+    if name == "general_d3_n24":
+        # general gates, single-qutrit: 24 layers, a Haar-random 3x3 unitary after each (up to
+        # 9 Weyl terms, MPO bond <= 9), chi_max 64, cutoff 1e-10, identity + 511 random candidates
+        nn = 24 if n is None else n
+        seed = 7003
+        c = general_circuit(3, nn, nn, 1, seed)
+        return Workload(name, c, candidate_words(3, 512, seed), chi_max=64, cutoff=1e-10)
+    if name == "general_d2_n24":
+        # general gates, two-qubit: 24 layers, a Haar-random 4x4 unitary on two neighbouring
+        # qubits after each (up to 16 Weyl terms), chi_max 64, cutoff 1e-10, the 720 elements of
+        # Sp(4, Z_2) as candidates
+        nn = 24 if n is None else n
+        seed = 7002
+        c = general_circuit(2, nn, nn, 2, seed)
+        return Workload(name, c, [], chi_max=64, cutoff=1e-10, candidate_set="all_sp4")
     raise KeyError(name)
 
 
