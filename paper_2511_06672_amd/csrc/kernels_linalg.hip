@@ -391,20 +391,17 @@ constexpr int kSolveThreads = 512;  // threads per 32x32 sub-problem (block and 
 constexpr int BJ2 = 2 * kBlk; // pair size (32)
 constexpr int SLD = BJ2 + 1;  // LDS leading dimension (plane layout)
 
-// Kernel A: pair k of outer step `step` solves its 32x32 sub-problem (blocks I, J) and writes the
-// accumulated rotation to V + k*32*32 (row-major) with a rotated flag.  The first step of an
-// outer sweep runs a full round-robin sweep over the 32 indices (covering the pairs inside each
-// block); later steps rotate only the 16 x 16 inter-block pairs.  Over one outer sweep every
-// index pair is visited once.
-__global__ __launch_bounds__(512) void k_jblock_solve(const z64* __restrict__ Gp, int mp, int nb, int step, double thr,
-                                                      double tol, double skip, int rel, double floor2,
-                                                      z64* __restrict__ Vout, int* __restrict__ pair_flag,
-                                                      int* __restrict__ any_flag) {
-  constexpr int PL = BJ2 * SLD;
-  __shared__ double h0r[PL], h0i[PL], h1r[PL], h1i[PL], vr[PL], vi[PL];
-  __shared__ unsigned char tab[31 * 32];
-  __shared__ int any, need;
-  const int k = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+// Solve step of a round: pair k of outer step `step` solves its 32x32 sub-problem (blocks I, J)
+// and writes the accumulated rotation to V + k*32*32 (row-major) with a rotated flag.  The first
+// step of an outer sweep runs a full round-robin sweep over the 32 indices (covering the pairs
+// inside each block); later steps rotate only the 16 x 16 inter-block pairs.  Over one outer
+// sweep every index pair is visited once.  LDS: six 32 x SLD planes.
+__device__ void solve_pair(int k, const z64* __restrict__ Gp, int mp, int nb, int step, double thr, double tol,
+                           double skip, int rel, double floor2, z64* __restrict__ Vout, int* __restrict__ pair_flag,
+                           int* __restrict__ any_flag, double* __restrict__ h0r, double* __restrict__ h0i,
+                           double* __restrict__ h1r, double* __restrict__ h1i, double* __restrict__ vr,
+                           double* __restrict__ vi, unsigned char* __restrict__ tab, int& any, int& need) {
+  const int t = threadIdx.x, nt = blockDim.x;
   int I, J;
   rr_pair(k, step, nb, I, J);
   const bool full = (step == 0);
@@ -478,10 +475,11 @@ __device__ __forceinline__ int pair_index(int P, int i, int step, int nb) {
 }
 
 // Kernel B: tiles (P, Q), P <= Q, of G <- V_P^H G V_Q (the (Q, P) tile is written as the conjugate
-// transpose) and row tiles of U <- U V_Q (32x32 tiles).
+// transpose) and row tiles of U <- U V_Q (32x32 tiles); tile index blockIdx.x + tile0, the G
+// tiles first.
 __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64* __restrict__ Up, int mp, int nb,
                                                       int step, const z64* __restrict__ V,
-                                                      const int* __restrict__ pair_flag) {
+                                                      const int* __restrict__ pair_flag, int tile0) {
   extern __shared__ double smem[];
   double* a_re = smem;
   double* a_im = a_re + BJ2 * SLD;
@@ -492,7 +490,7 @@ __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64*
   const int t = threadIdx.x, nt = blockDim.x;
   const int lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
-  int tile = blockIdx.x;
+  int tile = blockIdx.x + tile0;
   d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
   if (tile < ngt) {
     int P = 0, rem = tile;
@@ -570,6 +568,62 @@ __global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64*
       Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, col, step, nb)] = z64{accr[q], acci[q]};
     }
   }
+}
+
+// One 32x32 row tile (R, Q) of U <- U V_Q with 512 threads: all threads stage the operands, the
+// first four waves multiply (planes re/im in a_*/b_*, 32 x SLD each).
+__device__ void u_tile(z64* __restrict__ Up, int mp, int nb, int step, const z64* __restrict__ V,
+                       const int* __restrict__ pair_flag, int tile, double* __restrict__ a_re,
+                       double* __restrict__ a_im, double* __restrict__ b_re, double* __restrict__ b_im) {
+  const int half = nb / 2;
+  const int R = tile / half, Q = tile % half;
+  if (!pair_flag[Q]) return;  // uniform over the block
+  const int t = threadIdx.x, nt = blockDim.x;
+  const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
+  for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+    const int row = idx / BJ2, kk = idx % BJ2;
+    const z64 v = Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, kk, step, nb)];
+    a_re[kk * SLD + row] = v.re;
+    a_im[kk * SLD + row] = v.im;
+    const z64 q = VQ[idx];
+    b_re[row * SLD + kk] = q.re;
+    b_im[row * SLD + kk] = q.im;
+  }
+  __syncthreads();
+  if (t < 256) {
+    const int lane = t & 63, w = t >> 6;
+    const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+    d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+    mm32(a_re, a_im, b_re, b_im, false, accr, acci);
+    for (int q = 0; q < 4; ++q) {
+      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
+      Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, col, step, nb)] = z64{accr[q], acci[q]};
+    }
+  }
+}
+
+// Kernel A of a round: blocks 0..half-1 solve the sub-problems of outer step `step` (rotations
+// to Vout, flags to pair_flag); when ustep >= 0 the remaining blocks apply the previous round's
+// rotations (Vprev, flags pflag_prev, its outer step ustep) to the eigenvector accumulator, one
+// row tile each.  The accumulator is not read by the solve or by the G update, so for large m
+// its update for round r runs beside round r+1's latency-bound solve on the otherwise idle CUs;
+// the rotation and flag buffers alternate between rounds.
+__global__ __launch_bounds__(512) void k_jblock_solve(const z64* __restrict__ Gp, z64* __restrict__ Up, int mp, int nb,
+                                                      int step, double thr, double tol, double skip, int rel,
+                                                      double floor2, z64* __restrict__ Vout, int* __restrict__ pair_flag,
+                                                      int* __restrict__ any_flag, int ustep,
+                                                      const z64* __restrict__ Vprev,
+                                                      const int* __restrict__ pflag_prev) {
+  constexpr int PL = BJ2 * SLD;
+  __shared__ double h0r[PL], h0i[PL], h1r[PL], h1i[PL], vr[PL], vi[PL];
+  __shared__ unsigned char tab[31 * 32];
+  __shared__ int any, need;
+  const int half = nb / 2;
+  if ((int)blockIdx.x < half)
+    solve_pair(blockIdx.x, Gp, mp, nb, step, thr, tol, skip, rel, floor2, Vout, pair_flag, any_flag, h0r, h0i, h1r, h1i,
+               vr, vi, tab, any, need);
+  else if (ustep >= 0)
+    u_tile(Up, mp, nb, ustep, Vprev, pflag_prev, blockIdx.x - half, h0r, h0i, h1r, h1i);
 }
 
 __global__ void k_pad_copy(const z64* __restrict__ G, int m, int ldg, z64* __restrict__ Gp, int mp,
@@ -842,15 +896,30 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   const int half = nb / 2;
   int sweeps = 0;
   bool conv = false;
+  // rotation and flag buffers of round r: V + (r & 1) * half * 32 * 32, flags + 1 + (r & 1) * 128
+  // (half <= m_pad / 32 <= 128; the V region holds m_pad / 16 blocks of 32 x 32 and more)
+  GC_CHECK(half <= 128, GCAMPS_ECAPACITY, "eigensolver: matrix side exceeds 4096");
+  auto vbuf = [&](long r) { return w.V + (size_t)(r & 1) * half * BJ2 * BJ2; };
+  auto fbuf = [&](long r) { return w.flags + 1 + (r & 1) * 128; };
+  const int gtiles = half * (half + 1) / 2, utiles = (mp / BJ2) * half;
+  // Deferring round r's U update into round r + 1's solve launch pays once the apply launch is
+  // throughput-bound: measured 11% faster per decomposition at m = 1536, 3% slower at m = 768
+  // (there the apply is latency-bound and the U tiles only contend with the solve).
+  const bool defer = mp > 1024;
+  long round = 0;  // rounds launched so far; with defer, round - 1 still owes its U update
+  int prev_step = -1;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     GC_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
-    for (int step = 0; step < nb - 1; ++step) {
-      hipLaunchKernelGGL(k_jblock_solve, dim3(half), dim3(kSolveThreads), 0, s, Gp, mp, nb, step, thr, tol, skipv, rel, floor2, w.V,
-                         w.flags + 1, w.flags);
+    for (int step = 0; step < nb - 1; ++step, ++round) {
+      const bool owe = defer && round > 0;
+      hipLaunchKernelGGL(k_jblock_solve, dim3(half + (owe ? utiles : 0)), dim3(kSolveThreads), 0, s, Gp, Up, mp, nb,
+                         step, thr, tol, skipv, rel, floor2, vbuf(round), fbuf(round), w.flags, owe ? prev_step : -1,
+                         owe ? vbuf(round - 1) : nullptr, owe ? fbuf(round - 1) : nullptr);
       GC_LAUNCH_CHECK();
-      int tiles = half * (half + 1) / 2 + (mp / BJ2) * half;
-      hipLaunchKernelGGL(k_jblock_apply, dim3(tiles), dim3(256), lds_b, s, Gp, Up, mp, nb, step, w.V, w.flags + 1);
+      hipLaunchKernelGGL(k_jblock_apply, dim3(defer ? gtiles : gtiles + utiles), dim3(256), lds_b, s, Gp, Up, mp, nb,
+                         step, vbuf(round), fbuf(round), 0);
       GC_LAUNCH_CHECK();
+      prev_step = step;
     }
     ++sweeps;
     int any = 0;
@@ -860,6 +929,11 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
       conv = true;
       break;
     }
+  }
+  if (defer && round > 0) {  // the last round's U update
+    hipLaunchKernelGGL(k_jblock_apply, dim3(utiles), dim3(256), lds_b, s, Gp, Up, mp, nb, prev_step, vbuf(round - 1),
+                       fbuf(round - 1), gtiles);
+    GC_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_unpad, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gp, Up, m, mp, U, ldu, lam);
   GC_LAUNCH_CHECK();
