@@ -334,17 +334,21 @@ __global__ __launch_bounds__(256) void k_gen_rotated(int d_rt, int chil, int chi
 }
 
 // Purity tiles: for candidate slot `ls` of the chunk, tile (I, J), I <= J, of rho = N N^H over the
-// k columns, on MFMA (16x16x4, FP32 or FP64 accumulate).  Each of the four waves owns a quadrant
-// of BL x BL 16x16 blocks (TT = 32 * BL).  The FP32 instance uses three real products per
-// complex product (its three accumulator sets need the whole register file: one workgroup per
-// CU); the FP64 instance (window re-score) uses four and runs two workgroups per CU.  The epilogue writes sum |rho_tile|^2 (doubled off the
-// diagonal) and the tile's trace to partial[slot][tile].
-template <typename T, int BL>
-__global__ __launch_bounds__(256, (std::is_same<T, float>::value ? 1 : 2)) void k_gram_purity(int m, int k, const cx<T>* __restrict__ nbase, size_t stride,
+// k columns, on MFMA (16x16x4, FP32 or FP64 accumulate).  The NW waves form two rows of NW / 2:
+// each owns BL x (2 BL / (NW / 2)) 16x16 blocks of the TT x TT tile (TT = 32 * BL).  The FP32
+// instance uses three real products per complex product and runs eight waves, one workgroup per
+// CU: two waves per SIMD, so one wave's LDS waits overlap the other's MFMAs (7% faster than four
+// waves holding the whole register file).  The FP64 instance (window re-score) uses four
+// products and four waves, two workgroups per CU.  The epilogue writes sum |rho_tile|^2 (doubled
+// off the diagonal) and the tile's trace to partial[slot][tile].
+template <typename T, int BL, int NW>
+__global__ __launch_bounds__(64 * NW, (std::is_same<T, float>::value ? 1 : 2)) void k_gram_purity(int m, int k, const cx<T>* __restrict__ nbase, size_t stride,
                                                      int c0, int cnt, const int* __restrict__ nlimit, int ntp,
                                                      double* __restrict__ partial) {
   typedef typename AccT<T>::type acc_t;
   constexpr int TT = 32 * BL, KC = 16, PAD = TT + 4;
+  constexpr int NT = 64 * NW, WC = NW / 2;          // threads; waves along the columns (two rows)
+  constexpr int BLR = BL, BLC = 2 * BL / WC;         // 16x16 blocks per wave: rows, columns
   // XCD-aware order: workgroup L runs on XCD L mod 8, so the ntp tiles of one candidate are
   // given consecutive slots of one XCD and share its L2 (candidates are padded to a multiple
   // of 8; the padding exits at once).
@@ -362,27 +366,27 @@ __global__ __launch_bounds__(256, (std::is_same<T, float>::value ? 1 : 2)) void 
   // then stored into the other stage; one barrier per chunk
   __shared__ T As[2][2][KC][PAD];
   __shared__ T Bs[2][2][KC][PAD];
-  __shared__ double red[256];
+  __shared__ double red[NT];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = (w >> 1) * (TT / 2), wc = (w & 1) * (TT / 2);
+  const int wr = (w / WC) * (TT / 2), wc = (w % WC) * (TT / WC);
   // FP32: three real products per complex product, T1 = Ar Br^T, T2 = Ai Bi^T (B holds -Im),
   // T3 = (Ar + Ai)(Br + Bi)^T; re = T1 - T2, im = T3 - T1 - T2.  FP64: re and im directly.
   constexpr bool k3 = std::is_same<T, float>::value;
-  acc_t accr[BL][BL], acci[BL][BL], acc3[k3 ? BL : 1][k3 ? BL : 1];
-  for (int i = 0; i < BL; ++i)
-    for (int j = 0; j < BL; ++j)
+  acc_t accr[BLR][BLC], acci[BLR][BLC], acc3[k3 ? BLR : 1][k3 ? BLC : 1];
+  for (int i = 0; i < BLR; ++i)
+    for (int j = 0; j < BLC; ++j)
       for (int q = 0; q < 4; ++q) {
         accr[i][j][q] = T(0);
         acci[i][j][q] = T(0);
         if constexpr (k3) acc3[i][j][q] = T(0);
       }
   const int r0 = I * TT, q0 = J * TT;
-  constexpr int U = TT * KC / 256;
+  constexpr int U = TT * KC / NT;
   cx<T> pa[U], pb[U];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = t + 256 * u;
+      const int e = t + NT * u;
       const int row = e / KC, kk = e % KC;
       const int col = k0 + kk;
       pa[u] = cx<T>{T(0), T(0)};
@@ -396,7 +400,7 @@ __global__ __launch_bounds__(256, (std::is_same<T, float>::value ? 1 : 2)) void 
   auto stash = [&](int sg) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = t + 256 * u;
+      const int e = t + NT * u;
       const int row = e / KC, kk = e % KC;
       As[sg][0][kk][row] = pa[u].re;
       As[sg][1][kk][row] = pa[u].im;
@@ -414,28 +418,28 @@ __global__ __launch_bounds__(256, (std::is_same<T, float>::value ? 1 : 2)) void 
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       const int ka = kk + (lane >> 4);
-      T ar[BL], ai[BL], br[BL], bi[BL];
-      for (int i = 0; i < BL; ++i) {
+      T ar[BLR], ai[BLR], br[BLC], bi[BLC];
+      for (int i = 0; i < BLR; ++i) {
         ar[i] = As[sg][0][ka][wr + i * 16 + (lane & 15)];
         ai[i] = As[sg][1][ka][wr + i * 16 + (lane & 15)];
-        br[i] = Bs[sg][0][ka][wc + i * 16 + (lane & 15)];
-        bi[i] = Bs[sg][1][ka][wc + i * 16 + (lane & 15)];
+      }
+      for (int j = 0; j < BLC; ++j) {
+        br[j] = Bs[sg][0][ka][wc + j * 16 + (lane & 15)];
+        bi[j] = Bs[sg][1][ka][wc + j * 16 + (lane & 15)];
       }
       if constexpr (k3) {
-        T sa[BL], sb[BL];
-        for (int i = 0; i < BL; ++i) {
-          sa[i] = ar[i] + ai[i];
-          sb[i] = br[i] + bi[i];
-        }
-        for (int i = 0; i < BL; ++i)
-          for (int j = 0; j < BL; ++j) {
+        T sa[BLR], sb[BLC];
+        for (int i = 0; i < BLR; ++i) sa[i] = ar[i] + ai[i];
+        for (int j = 0; j < BLC; ++j) sb[j] = br[j] + bi[j];
+        for (int i = 0; i < BLR; ++i)
+          for (int j = 0; j < BLC; ++j) {
             accr[i][j] = mfma_t(ar[i], br[j], accr[i][j]);   // T1
             acci[i][j] = mfma_t(ai[i], bi[j], acci[i][j]);   // T2
             acc3[i][j] = mfma_t(sa[i], sb[j], acc3[i][j]);   // T3
           }
       } else {
-        for (int i = 0; i < BL; ++i)
-          for (int j = 0; j < BL; ++j) {
+        for (int i = 0; i < BLR; ++i)
+          for (int j = 0; j < BLC; ++j) {
             accr[i][j] = mfma_t(ar[i], br[j], accr[i][j]);
             accr[i][j] = mfma_t(-ai[i], bi[j], accr[i][j]);
             acci[i][j] = mfma_t(ar[i], bi[j], acci[i][j]);
@@ -449,8 +453,8 @@ __global__ __launch_bounds__(256, (std::is_same<T, float>::value ? 1 : 2)) void 
   }
   double pur = 0.0, tr = 0.0;
   const double wgt = (I == J) ? 1.0 : 2.0;
-  for (int i = 0; i < BL; ++i)
-    for (int j = 0; j < BL; ++j)
+  for (int i = 0; i < BLR; ++i)
+    for (int j = 0; j < BLC; ++j)
       for (int q = 0; q < 4; ++q) {
         const int row = r0 + wr + i * 16 + mfma_row<T>(lane, q);
         const int col = q0 + wc + j * 16 + (lane & 15);
@@ -986,7 +990,7 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
         hipLaunchKernelGGL((k_gen_rotated<double, 0>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
                            nlimit, nb, stride);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
-      hipLaunchKernelGGL((k_gram_purity<double, 2>), gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
+      hipLaunchKernelGGL((k_gram_purity<double, 2, 4>), gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
                          partial);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
     } else {
@@ -1001,7 +1005,7 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
         hipLaunchKernelGGL((k_gen_rotated<float, 0>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
                            nlimit, nb, stride);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
-      hipLaunchKernelGGL((k_gram_purity<float, 4>), gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
+      hipLaunchKernelGGL((k_gram_purity<float, 4, 8>), gp, dim3(512), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
                          partial);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
     }
