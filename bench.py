@@ -538,8 +538,8 @@ def main():
                     help="headline: skip the replica-tensor-scored comparison run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in the design notes.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
+              "multi-GPU execution.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         main_batch(args)

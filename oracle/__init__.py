@@ -20,7 +20,7 @@ Everything is complex128 / exact integers, written from the paper's definitions
 * ``statevector`` a dense state-vector simulator used as brute-force reference (§2.1)
 * ``adjoint``     gradients of a Weyl-observable loss w.r.t. phase-gate angles
 
-Parity status of every function is listed in the design notes; functions whose
-results are fixed only by the heuristic rules chosen for the truncated regime
-(tie-break, truncation cut placement) say "parity unpinned" in their docstring.
+Functions whose results are fixed only by the heuristic rules chosen for the
+truncated regime (tie-break, truncation cut placement) say "parity unpinned" in
+their docstring.
 """

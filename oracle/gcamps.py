@@ -20,8 +20,8 @@ Bottom loop for a diagonal phase gate U = diag(e^{i phi_j}) on site k:
       after a sweep that keeps the identity everywhere or after max_sweeps.
       (The paper gives the idea of reducing entanglement with two-qudit Cliffords
       and an exhaustive search; the entropy measure, tie rule and sweep schedule are
-      the readings listed in the design notes.  Parity of the truncated regime is
-      "parity unpinned": it is fixed only by these rules.)
+      this package's readings of it.  Parity of the truncated regime is "parity
+      unpinned": it is fixed only by these rules.)
 
 Observables (§3): <psi|W|psi> = <MPS|C^dagger W C|MPS> by transfer matrices;
 Re<W> is the expectation of the Hermitian O = (W + W^dagger)/2.

@@ -130,9 +130,9 @@ class Circuit:
 def t_gate_phases(d: int) -> Tuple[float, ...]:
     """Angles of the non-Clifford T gate used by the workloads.
 
-    d = 2: diag(1, e^{i pi/4}).  d = 3: diag(1, e^{2 pi i/9}, e^{-2 pi i/9}) (the
-    qutrit T gate whose cube is Z; the paper's printed qutrit matrix is read as
-    this one, see the design notes).
+    d = 2: diag(1, e^{i pi/4}).  d = 3: diag(1, e^{2 pi i/9}, e^{-2 pi i/9}), the
+    qutrit T gate whose cube is Z (the qutrit matrix printed in §2.3.2 does not have
+    that property and is taken to be garbled).
     """
     if d == 2:
         return (0.0, math.pi / 4)
