@@ -127,3 +127,32 @@ def test_many_lanes_on_the_batch_workload():
         st, _ = single_state(g, bw.circuits[i], cfgs[i], cs)
         assert res[i]["fidelity"] == st.fidelity()
         assert res[i]["bond_dims"] == st.bond_dims()
+
+
+def test_batch_workload_sample_against_oracle_reference():
+    """The first 32 circuits of the batch workload in one batch on 4 lanes (the benchmark's
+    configuration: FP32 scoring with the FP64 near-tie window); eight of them, from product-like
+    to one that reaches chi_max = 128 with truncation, against the oracle's references
+    (tests/golden/batch_d3_sample_oracle.json, written by make_batch_reference.py from oracle/
+    only): choices and bond dimensions exact, F_est within F_TOL, <Z_j> within Z_TOL."""
+    import json
+    import os
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import batch_workload
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch_d3_sample_oracle.json")))
+    bw = batch_workload(count=32)
+    assert ref["chi_max"] == bw.chi_max and ref["candidates"] == len(bw.candidates)
+    print("[gpu-case] batch workload, 32 circuits on 4 lanes, oracle sample", flush=True)
+    cfgs = [g.make_config(3, c.n, bw.chi_max, bw.cutoff, score_prec=g.SCORE_FP32, near_tie=1e-4,
+                          max_sweeps=bw.max_sweeps, max_candidates=len(bw.candidates)) for c in bw.circuits]
+    res, _ = g.batch_run(bw.circuits, cfgs, g.CandSet(3, bw.candidates), lanes=4)
+    for r in ref["circuits"]:
+        i = r["index"]
+        mine = res[i]
+        print(f"[gpu-case] circuit {i}: n={r['n']} T={r['t_gates']}", flush=True)
+        assert mine["status"] == 0
+        assert [list(map(int, e)) for e in mine["choices"]] == r["choices"], f"choices differ in circuit {i}"
+        assert mine["bond_dims"] == r["bond_dims"]
+        assert abs(mine["fidelity"] - r["f_est"]) <= F_TOL * r["f_est"]
+        zo = np.array(r["z_re"]) + 1j * np.array(r["z_im"])
+        assert np.max(np.abs(mine["z_expect"] - zo)) <= Z_TOL
