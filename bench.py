@@ -525,7 +525,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--workload", choices=["headline", "batch", "grad", "paper", "gates", "copy"], default="headline")
     ap.add_argument("--batch-count", type=int, default=256)
-    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--lanes", type=int, default=8,
+                    help="batch: concurrent lanes (host threads with their own streams)")
     ap.add_argument("--batch-chunk", type=int, default=0,
                     help="batch: run the circuits in chunks of this many (progress lines; 0 = all at once)")
     ap.add_argument("--serial-check", action="store_true", help="batch: also run on one lane")
@@ -542,6 +543,9 @@ def main():
               "multi-GPU execution.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
+        # one hardware queue per lane (HIP gives a process 4 by default); set before the HIP
+        # runtime starts, unless the caller chose a value
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(max(4, args.lanes), 16)))
         main_batch(args)
         return
     if args.workload == "grad":

@@ -130,7 +130,7 @@ def test_many_lanes_on_the_batch_workload():
 
 
 def test_batch_workload_sample_against_oracle_reference():
-    """The first 32 circuits of the batch workload in one batch on 4 lanes (the benchmark's
+    """The first 32 circuits of the batch workload in one batch on 8 lanes (the benchmark's
     configuration: FP32 scoring with the FP64 near-tie window); eight of them, from product-like
     to one that reaches chi_max = 128 with truncation, against the oracle's references
     (tests/golden/batch_d3_sample_oracle.json, written by make_batch_reference.py from oracle/
@@ -142,10 +142,10 @@ def test_batch_workload_sample_against_oracle_reference():
     ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch_d3_sample_oracle.json")))
     bw = batch_workload(count=32)
     assert ref["chi_max"] == bw.chi_max and ref["candidates"] == len(bw.candidates)
-    print("[gpu-case] batch workload, 32 circuits on 4 lanes, oracle sample", flush=True)
+    print("[gpu-case] batch workload, 32 circuits on 8 lanes, oracle sample", flush=True)
     cfgs = [g.make_config(3, c.n, bw.chi_max, bw.cutoff, score_prec=g.SCORE_FP32, near_tie=1e-4,
                           max_sweeps=bw.max_sweeps, max_candidates=len(bw.candidates)) for c in bw.circuits]
-    res, _ = g.batch_run(bw.circuits, cfgs, g.CandSet(3, bw.candidates), lanes=4)
+    res, _ = g.batch_run(bw.circuits, cfgs, g.CandSet(3, bw.candidates), lanes=8)
     for r in ref["circuits"]:
         i = r["index"]
         mine = res[i]
