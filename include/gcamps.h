@@ -202,6 +202,21 @@ int32_t gcamps_set_candset(gcamps_ctx* ctx, const gcamps_candset* set);
  * candidate count doubles.  Errors: EINVAL (bond outside [0, n-2], no candidate set, cap too
  * small), EDEVICE. */
 int32_t gcamps_score_bond(gcamps_ctx* ctx, int32_t bond, double* out, int64_t cap);
+/* The factorisation every split of the bottom loop uses (§2.4: the SVD of a two-site tensor
+ * reshaped across the cut, truncated by the ctx's rule: discarded weight <= cutoff, rank floor
+ * 1e-13 sigma_0, at most chi_max kept, a cut inside a degenerate group moved below it), applied
+ * to a caller's matrix so that it can be checked on its own.  m_host: p x q complex128,
+ * row-major, interleaved (re, im), borrowed.  Requires min(p, q) and p * q within the ctx's
+ * capacity (min(p, q) <= chi_max * max(d, max_gate_terms), p * q <= that times d times itself).
+ * Outputs (host): sig_out[min(p, q)] all singular values in descending order; *kept the rank
+ * kept; *eps the discarded weight sum_{i >= kept} sigma_i^2 / sum_i sigma_i^2; if non-NULL,
+ * l_out[p * kept] the left factor U_k (orthonormal columns, row-major complex128) and
+ * r_out[kept * q] the right factor diag(s_k) V_k^dagger with s_k the kept singular values
+ * scaled to unit norm (row-major complex128), so that L R = M_k / |M_k|.  The state of the ctx
+ * is not changed.  Errors: EINVAL (null pointer, p or q < 1), ECAPACITY, EUNSUPPORTED (ctx of a
+ * gradient recording), ENUMERIC, EDEVICE. */
+int32_t gcamps_factorize(gcamps_ctx* ctx, const double* m_host, int32_t p, int32_t q, double* sig_out,
+                         int32_t* kept, double* eps, double* l_out, double* r_out);
 
 int32_t gcamps_disentangle(gcamps_ctx* ctx, const gcamps_candset* set, int32_t* out_sweeps,
                            int32_t* out_changed_bonds);

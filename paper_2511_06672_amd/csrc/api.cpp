@@ -419,6 +419,29 @@ int32_t gcamps_score_bond(gcamps_ctx* ctx, int32_t bond, double* out, int64_t ca
   });
 }
 
+int32_t gcamps_factorize(gcamps_ctx* ctx, const double* m_host, int32_t p, int32_t q, double* sig_out,
+                         int32_t* kept, double* eps, double* l_out, double* r_out) {
+  return guarded(ctx, [&] {
+    GC_CHECK(ctx && m_host && sig_out && kept && eps, GCAMPS_EINVAL, "null argument");
+    GC_CHECK(p >= 1 && q >= 1, GCAMPS_EINVAL, "matrix must be at least 1 x 1");
+    GC_CHECK(ctx->tape == nullptr && ctx->rank_rec == nullptr && ctx->rank_frz == nullptr, GCAMPS_EUNSUPPORTED,
+             "factorize is not available on a gradient recording");
+    const size_t m = (size_t)std::min(p, q), pq = (size_t)p * q;
+    GC_CHECK(m <= ctx->lay.mcap && pq <= ctx->lay.slot_elems, GCAMPS_ECAPACITY,
+             "matrix exceeds the ctx's factorisation capacity");
+    GC_HIP(hipMemcpyAsync(ctx->theta, m_host, pq * sizeof(z64), hipMemcpyHostToDevice, ctx->stream));
+    const DevStatus h = ctx->factorize(ctx->theta, p, q, 0, 1, ctx->Lbuf, ctx->Rbuf);
+    GC_HIP(hipMemcpyAsync(sig_out, ctx->sig, m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (l_out)
+      GC_HIP(hipMemcpyAsync(l_out, ctx->Lbuf, (size_t)p * h.kept * sizeof(z64), hipMemcpyDeviceToHost, ctx->stream));
+    if (r_out)
+      GC_HIP(hipMemcpyAsync(r_out, ctx->Rbuf, (size_t)h.kept * q * sizeof(z64), hipMemcpyDeviceToHost, ctx->stream));
+    GC_HIP(hipStreamSynchronize(ctx->stream));
+    *kept = h.kept;
+    *eps = h.eps;
+  });
+}
+
 int32_t gcamps_disentangle(gcamps_ctx* ctx, const gcamps_candset* set, int32_t* out_sweeps,
                            int32_t* out_changed_bonds) {
   return guarded(ctx, [&] {

@@ -26,7 +26,8 @@ CRITERION_RENYI2, CRITERION_BOND_DIM = 0, 1
 SYMBOLS = [
     "gcamps_workspace_bytes", "gcamps_init", "gcamps_destroy", "gcamps_apply_clifford",
     "gcamps_apply_clifford_layer", "gcamps_apply_phase_rotation", "gcamps_apply_gate", "gcamps_candset_create",
-    "gcamps_candset_destroy", "gcamps_clifford_words", "gcamps_set_candset", "gcamps_score_bond", "gcamps_disentangle", "gcamps_expectation",
+    "gcamps_candset_destroy", "gcamps_clifford_words", "gcamps_set_candset", "gcamps_score_bond",
+    "gcamps_factorize", "gcamps_disentangle", "gcamps_expectation",
     "gcamps_statevector", "gcamps_amplitude", "gcamps_get_tableau", "gcamps_get_bond_dims",
     "gcamps_get_fidelity", "gcamps_get_choice_log", "gcamps_get_site", "gcamps_get_stats",
     "gcamps_batch_workspace_bytes", "gcamps_batch_run", "gcamps_grad_record", "gcamps_grad_loss",
@@ -93,6 +94,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gcamps_candset_destroy": [P],
         "gcamps_set_candset": [P, P],
         "gcamps_score_bond": [P, I32, C.POINTER(D), I64],
+        "gcamps_factorize": [P, C.POINTER(D), I32, I32, C.POINTER(D), C.POINTER(I32), C.POINTER(D),
+                             C.POINTER(D), C.POINTER(D)],
         "gcamps_clifford_words": [I32, I32, C.POINTER(I32), I32, C.POINTER(C.c_uint8), I64, C.POINTER(I32),
                                   C.POINTER(I64)],
         "gcamps_disentangle": [P, P, C.POINTER(I32), C.POINTER(I32)],
@@ -264,6 +267,26 @@ class State:
         buf = (C.c_double * cnt)()
         _check(lib().gcamps_score_bond(self.handle, bond, buf, cnt))
         return np.frombuffer(buf, dtype=np.float64).copy()
+
+    def factorize(self, m, factors: bool = False):
+        """The split's factorisation of a host matrix m (p x q complex) under this ctx's
+        truncation rule (gcamps_factorize).  Returns (singular values in descending order,
+        kept rank, discarded weight, L, R); L (p x kept) and R (kept x q) only with factors,
+        else None."""
+        m = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+        p, q = m.shape
+        mn = min(p, q)
+        sig = np.zeros(mn)
+        kept, eps = C.c_int32(0), C.c_double(0.0)
+        lbuf = np.zeros(p * mn, dtype=np.complex128) if factors else None
+        rbuf = np.zeros(mn * q, dtype=np.complex128) if factors else None
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None  # noqa: E731
+        _check(lib().gcamps_factorize(self.handle, dp(m), p, q, dp(sig), C.byref(kept), C.byref(eps), dp(lbuf),
+                                      dp(rbuf)))
+        k = kept.value
+        L = lbuf[:p * k].reshape(p, k) if factors else None
+        R = rbuf[:k * q].reshape(k, q) if factors else None
+        return sig, k, eps.value, L, R
 
     def disentangle(self, cs: Optional[CandSet] = None):
         sw, ch = C.c_int32(0), C.c_int32(0)

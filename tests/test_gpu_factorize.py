@@ -1,0 +1,125 @@
+"""The split's factorisation on its own (gcamps_factorize: Gram on MFMA, block-Jacobi eigensolver,
+truncation rule, emit) against LAPACK singular values and the oracle's truncation rule, from
+1 x 7 up to the library's maximum matrix side, 4096 (a ctx with chi_max = 2048 and d = 2): there
+the eigensolver runs 128 sub-problems per round and defers each round's eigenvector update into
+the next solve launch.
+
+Bars.  With sigma_0 the largest singular value:
+- kept rank equals the oracle's rule on the LAPACK values (the cases are built with no value
+  near a decision threshold);
+- every sigma_i^2 within 1e-11 sigma_0^2 of LAPACK's: the FP64 Gram (sums of up to 4096
+  products) and the Jacobi rotations fix its eigenvalues to a small multiple of
+  m * eps * sigma_0^2, and 1e-11 is 22 m eps at m = 4096 (measured: 1.7e-12 there);
+  the kept values within 1e-12 sigma_0;
+- discarded weight within 1e-9 relative (1e-12 absolute);
+- factors: L has orthonormal columns (1e-12) and R = L^dagger M / |s_k| (1e-10 of the largest
+  entry), which with the first bar makes L R the normalised rank-k truncation of M.
+With cutoff 0 the rank floor decides, through the relative-accuracy second pass: an exactly
+rank-50 matrix keeps 50 with its null values below the floor, and a graded spectrum
+sigma_i = 10^(-0.3 i) keeps 44 (values down to 1.3e-13 sigma_0), checked against the
+constructed spectrum itself.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.mps import rtrunc, svd
+
+pytestmark = pytest.mark.gpu
+CHI, CUT = 2048, 1e-10
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2511_06672_amd import gcamps
+    gcamps.lib()
+    return gcamps
+
+
+def state(g, cutoff):
+    return g.State(g.make_config(2, 2, CHI, cutoff, auto_disentangle=False, max_candidates=1))
+
+
+def gauss(rng, p, q):
+    return (rng.standard_normal((p, q)) + 1j * rng.standard_normal((p, q))) / np.sqrt(2)
+
+
+def check(g, st, m, cutoff, factors):
+    sig, k, eps, L, R = st.factorize(m, factors=factors)
+    ref = np.linalg.svd(m, compute_uv=False)
+    kr, er, _ = rtrunc(ref, cutoff, CHI)
+    s0 = ref[0]
+    assert k == kr
+    assert np.all(np.diff(sig) <= 0)
+    assert np.max(np.abs(sig[:k] - ref[:k])) <= 1e-12 * s0
+    assert np.max(np.abs(sig ** 2 - ref ** 2)) <= 1e-11 * s0 ** 2
+    assert abs(eps - er) <= max(1e-9 * er, 1e-12)
+    if factors:
+        assert L.shape == (m.shape[0], k) and R.shape == (k, m.shape[1])
+        assert np.max(np.abs(L.conj().T @ L - np.eye(k))) <= 1e-12
+        proj = L.conj().T @ m / np.linalg.norm(ref[:k])
+        assert np.max(np.abs(R - proj)) <= 1e-10 * np.max(np.abs(proj))
+    return k, sig, s0
+
+
+@pytest.mark.parametrize("p,q", [(1, 7), (7, 1), (5, 3), (33, 70), (70, 33), (300, 97), (1536, 1600)])
+def test_factorize_gaussian_shapes(g, p, q):
+    say(f"factorize gaussian {p} x {q}")
+    st = state(g, CUT)
+    rng = np.random.default_rng(1000 + p + 7 * q)
+    k, _, _ = check(g, st, gauss(rng, p, q), CUT, factors=True)
+    assert k == min(p, q)            # no value falls under the cutoff or the floor
+
+
+def test_factorize_cutoff_and_rank_floor(g):
+    rng = np.random.default_rng(77)
+    say("factorize rank 200 plus 1e-9 noise (the cutoff decides), 900 x 1200")
+    m = gauss(rng, 900, 200) @ gauss(rng, 200, 1200) / np.sqrt(200) + 1e-9 * gauss(rng, 900, 1200)
+    assert check(g, state(g, CUT), m, CUT, factors=True)[0] == 200
+    say("factorize exact rank 50, cutoff 0 (the rank floor decides after the second pass), 600 x 600")
+    m = gauss(rng, 600, 50) @ gauss(rng, 50, 600)
+    k, sig, s0 = check(g, state(g, 0.0), m, 0.0, factors=True)
+    assert k == 50 and np.max(sig[50:]) <= 1e-13 * s0
+
+
+def test_factorize_graded_spectrum_second_pass(g):
+    say("factorize graded spectrum 10^(-0.3 i), 128 x 128, cutoff 0")
+    st = state(g, 0.0)
+    rng = np.random.default_rng(78)
+    u, _, _ = svd(gauss(rng, 128, 128))
+    v, _, _ = svd(gauss(rng, 128, 128))
+    true = 10.0 ** (-0.3 * np.arange(128))
+    m = (u * true) @ v.conj().T
+    sig, k, eps, L, R = st.factorize(m, factors=True)
+    assert k == 44                   # sigma_43 = 10^-12.9 > 1e-13 sigma_0 > sigma_44 = 10^-13.2
+    # forming m rounds it by about eps * sqrt(128) sigma_0, which bounds how far its singular
+    # values can sit from the constructed ones
+    assert np.max(np.abs(sig[:k] - true[:k])) <= 2e-14
+    assert np.max(np.abs(L.conj().T @ L - np.eye(k))) <= 1e-12
+    assert abs(eps - np.sum(true[k:] ** 2) / np.sum(true ** 2)) <= 1e-15
+
+
+def test_factorize_maximum_size(g):
+    say("factorize gaussian 4096 x 4096 (maximum matrix side; chi_max 2048 keeps half)")
+    st = state(g, CUT)
+    rng = np.random.default_rng(4096)
+    assert check(g, st, gauss(rng, 4096, 4096), CUT, factors=False)[0] == CHI
+
+
+def test_factorize_errors(g):
+    say("factorize error paths")
+    st = state(g, CUT)
+    with pytest.raises(g.GcampsError) as e:
+        st.factorize(np.zeros((4097, 4097)))
+    assert e.value.code == -4        # ECAPACITY
+    with pytest.raises(g.GcampsError) as e:
+        st.factorize(np.zeros((3, 3)))
+    assert e.value.code == -6        # ENUMERIC: a zero matrix has nothing to keep
