@@ -497,6 +497,75 @@ def main_gates(args):
     print(json.dumps(out), flush=True)
 
 
+def run_mixed(g, name, prec, budget_s):
+    """One stress run (chi_max 1024, cutoff 1e-12) gate by gate until the circuit ends or the
+    time budget is spent; returns a summary dict."""
+    import torch
+    from paper_2511_06672_amd.workload import workload
+    wl = workload(name)
+    c = wl.circuit
+    cands = g.clifford_words(c.d, g.WORDS_ALL) if wl.candidate_set == "all_sp4" else wl.candidates
+    st = g.State(g.make_config(c.d, c.n, wl.chi_max, wl.cutoff, score_prec=prec, near_tie=NEAR_TIE,
+                               max_sweeps=wl.max_sweeps, max_candidates=len(cands)))
+    st.set_candset(g.CandSet(c.d, cands))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, first_full = 0, None
+    for layer in c.layers:
+        if time.perf_counter() - t0 > budget_s:
+            break
+        if layer.bricks:
+            st.apply_clifford_layer([b.site for b in layer.bricks], [b.word for b in layer.bricks])
+        for ph in layer.phases:
+            st.apply_phase_rotation(ph.site, ph.phi)
+            done += 1
+            mb = max(st.bond_dims())
+            if first_full is None and mb >= wl.chi_max:
+                first_full = done
+            if done % 4 == 0:
+                log(f"  [{name} {PREC_NAMES[prec]}] gate {done}/{c.n_phase_gates} maxchi {mb} "
+                    f"t={time.perf_counter() - t0:.1f}s")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    s = st.stats()
+    return {"gates": done, "of": c.n_phase_gates, "seconds": secs, "gates_per_s": done / secs,
+            "candidates": len(cands), "fidelity": st.fidelity(), "final_bond_dim_max": int(max(st.bond_dims())),
+            "first_gate_at_chi_max": first_full, "bonds_scored": int(s["bonds_scored"]),
+            "rescored_candidates": int(s["rescored"]),
+            "mean_window": (s["rescored"] / s["bonds_scored"]) if s["bonds_scored"] else None}
+
+
+def main_mixed(args):
+    """The stress runs: qubits n = 64 (one T per layer, all 720 elements of Sp(4, Z_2)) and
+    qutrits n = 48 (60 layers, identity + 719 random words), chi_max 1024, cutoff 1e-12, with the
+    scoring chosen by --score and the FP64 re-score window, each for at most --mixed-budget
+    seconds."""
+    import torch
+    from paper_2511_06672_amd import gcamps as g
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    prec = {"fp32": g.SCORE_FP32, "bf16": g.SCORE_BF16, "replica": g.SCORE_REPLICA}[args.score]
+    per, gates, secs = {}, 0, 0.0
+    for name in ["mixed_d3_n48", "mixed_d2_n64"]:
+        r = run_mixed(g, name, prec, args.mixed_budget)
+        log(f"{name}: {r['gates']}/{r['of']} gates in {r['seconds']:.1f} s, max bond {r['final_bond_dim_max']}")
+        per[name] = r
+        gates += r["gates"]
+        secs += r["seconds"]
+    out = {
+        "metric": "non-Clifford gates/sec, stress runs at chi_max = 1024",
+        "value": gates / secs, "unit": "non-Clifford gates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * secs, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": PREC_NAMES[prec] + " scoring / c128 commit",
+        "data": "synthetic (seeded brickwork circuits and candidate sets)",
+        "config": {"workload": "qutrits n=48, 60 layers, one T per layer, 720 candidates; qubits n=64, 64 layers, "
+                               "one T per layer, the 720 elements of Sp(4, Z_2); chi_max=1024, cutoff=1e-12; each run "
+                               f"for at most {args.mixed_budget:.0f} s",
+                   "parallelism": "1 GPU", "near_tie": NEAR_TIE},
+        "runs": per, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main_copy(args):
     """Plain device-to-device copies of a known size (counter calibration)."""
     import torch
@@ -523,15 +592,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["headline", "batch", "grad", "paper", "gates", "copy"], default="headline")
+    ap.add_argument("--workload", choices=["headline", "batch", "grad", "paper", "gates", "mixed", "copy"], default="headline")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--lanes", type=int, default=8,
                     help="batch: concurrent lanes (host threads with their own streams)")
     ap.add_argument("--batch-chunk", type=int, default=0,
                     help="batch: run the circuits in chunks of this many (progress lines; 0 = all at once)")
     ap.add_argument("--serial-check", action="store_true", help="batch: also run on one lane")
-    ap.add_argument("--score", choices=["fp32", "bf16"], default="fp32",
-                    help="headline: precision of the timed path's candidate scoring")
+    ap.add_argument("--mixed-budget", type=float, default=150.0,
+                    help="mixed: seconds per stress run (the run stops at the first gate boundary after it)")
+    ap.add_argument("--score", choices=["fp32", "bf16", "replica"], default="fp32",
+                    help="headline (fp32 or bf16) and mixed: the scoring of the timed path")
     ap.add_argument("--no-bf16", action="store_true", help="headline: skip the split-BF16 comparison run")
     ap.add_argument("--no-exhaustive", action="store_true",
                     help="headline: skip the run with the exhaustive disentangler set")
@@ -560,6 +631,9 @@ def main():
     if args.workload == "paper":
         main_paper(args)
         return
+    if args.workload == "mixed":
+        main_mixed(args)
+        return
 
     import numpy as np
     import torch
@@ -573,6 +647,9 @@ def main():
     log(f"workload {wl.name}: d={c.d} n={c.n} layers={len(c.layers)} gates={ngates} "
         f"chi_max={wl.chi_max} candidates={len(wl.candidates)}")
 
+    if args.score == "replica":
+        sys.exit("bench.py: the headline reports replica scoring as a side path (replica_path); "
+                 "--score replica applies to --workload mixed")
     prec = g.SCORE_BF16 if args.score == "bf16" else g.SCORE_FP32
     pname = "split-BF16-scored" if prec == g.SCORE_BF16 else "FP32-scored"
     for w in range(args.warmup):
