@@ -266,6 +266,14 @@ int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap,
  * centre tensor (identity kept), [15] algorithmic bytes read by the Gram-purity launches (each
  * rotated m x k matrix once). */
 int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[16]);
+/* Counters for the roofline of the compression and MPO steps (§2.4, §3), accumulated since
+ * gcamps_init: [0] factorisations; [1] their algorithmic flops, 4 (6 p q^2 + 20 q^3) per p x q
+ * SVD with p >= q (the R-SVD operation count, complex); [2] their device time in ms (Gram
+ * product to truncation rule, second pass included; the emit of the factors excluded);
+ * [3] MPO site launches; [4] their algorithmic bytes (each site tensor read once, its product
+ * written once, complex128); [5] their device time in ms; [6], [7] 0.  out: host array of 8
+ * doubles.  Synchronises the ctx's stream.  Errors: EINVAL, EDEVICE. */
+int32_t gcamps_get_kernel_stats(gcamps_ctx* ctx, double out[8]);
 
 /* ---------------------------------------------------------------------------
  * Batched independent circuits.

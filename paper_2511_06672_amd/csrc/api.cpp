@@ -243,6 +243,7 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
     GC_HIP(hipEventCreate(&c->ev1));
     GC_HIP(hipEventCreate(&c->ev2));
     GC_HIP(hipEventCreate(&c->ev3));
+    for (hipEvent_t* e : {&c->evf0, &c->evf1, &c->evm0, &c->evm1}) GC_HIP(hipEventCreate(e));
     c->gram_ev.resize(64);
     for (auto& e : c->gram_ev) GC_HIP(hipEventCreate(&e));
     // |0...0>: every site tensor (1, d, 1) = e_0, tableau C = I
@@ -707,6 +708,14 @@ int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap,
       GC_HIP(hipMemcpyAsync(out, ctx->site[site], cnt * sizeof(z64), hipMemcpyDeviceToHost, ctx->stream));
       GC_HIP(hipStreamSynchronize(ctx->stream));
     }
+  });
+}
+
+int32_t gcamps_get_kernel_stats(gcamps_ctx* ctx, double out[8]) {
+  return guarded(ctx, [&] {
+    GC_CHECK(ctx && out, GCAMPS_EINVAL, "null argument");
+    ctx->settle_mpo();
+    for (int i = 0; i < 8; ++i) out[i] = ctx->kstats[i];
   });
 }
 

@@ -121,12 +121,19 @@ struct gcamps_ctx {
   hipEvent_t stage_ev = nullptr;
   bool stage_pending = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  hipEvent_t evf0 = nullptr, evf1 = nullptr;  // around one factorisation (Gram to truncation rule)
+  hipEvent_t evm0 = nullptr, evm1 = nullptr;  // around one gate's MPO launches
+  bool mpo_pending = false;                   // evm0/evm1 recorded and not yet accumulated
   std::vector<hipEvent_t> gram_ev;  // event pairs around the Gram-purity launches of one bond
   // host state
   double f_est = 1.0;
   std::vector<int32_t> choice_log;
   int64_t gates = 0;
   double stats[16] = {0};
+  // [0] factorisations, [1] their SVD flops by the R-SVD count 4 (6 p q^2 + 20 q^3) (p >= q),
+  // [2] their device ms (Gram to truncation rule, second pass included), [3] MPO site launches,
+  // [4] MPO bytes (each site tensor read once and its product written once), [5] MPO device ms
+  double kstats[8] = {0};
   // gradient: recording and frozen replay (all null in ordinary use)
   std::vector<int32_t>* rank_rec = nullptr;          // kept rank of every factorisation
   std::vector<GateRec>* gate_rec = nullptr;          // Weyl string of every non-Clifford gate
@@ -145,6 +152,8 @@ struct gcamps_ctx {
     if (ev1) (void)hipEventDestroy(ev1);
     if (ev2) (void)hipEventDestroy(ev2);
     if (ev3) (void)hipEventDestroy(ev3);
+    for (hipEvent_t e : {evf0, evf1, evm0, evm1})
+      if (e) (void)hipEventDestroy(e);
     for (auto e : gram_ev) (void)hipEventDestroy(e);
   }
 
@@ -179,6 +188,7 @@ struct gcamps_ctx {
     GC_CHECK((size_t)m <= lay.mcap && (size_t)m * kW <= lay.slot_elems, GCAMPS_ECAPACITY,
              "factorisation exceeds workspace capacity");
     const z64 one = {1.0, 0.0};
+    GC_HIP(hipEventRecord(evf0, stream));
     if (wide)
       launch_zgemm(stream, 0, 1, m, m, q, M, q, M, q, G, m, one, 0, 1);
     else
@@ -198,6 +208,7 @@ struct gcamps_ctx {
     }
     launch_rownorm2(stream, B, m, kW, kW, sig2);
     launch_trunc(stream, sig2, m, cfg.cutoff, cfg.chi_max, mode, force_k, perm, sig, st);
+    GC_HIP(hipEventRecord(evf1, stream));
     DevStatus h;
     read_status(h);
     GC_CHECK(m > kSmallEig || h.converged, GCAMPS_ENUMERIC, "eigensolver did not converge");
@@ -213,11 +224,20 @@ struct gcamps_ctx {
       std::swap(B, B2);
       launch_rownorm2(stream, B, m, kW, kW, sig2);
       launch_trunc(stream, sig2, m, cfg.cutoff, cfg.chi_max, mode, force_k, perm, sig, st);
+      GC_HIP(hipEventRecord(evf1, stream));
       read_status(h);
       GC_CHECK(m > kSmallEig || h.converged, GCAMPS_ENUMERIC, "eigensolver did not converge (second pass)");
       stats[5] += 8.0 * (double)m * m * kW * 2.0;
     }
     GC_CHECK(std::isfinite(h.eps) && h.kept >= 1, GCAMPS_ENUMERIC, "factorisation produced non-finite values");
+    {  // both events have completed: read_status synchronised the stream after evf1
+      float fms = 0.0f;
+      GC_HIP(hipEventElapsedTime(&fms, evf0, evf1));
+      const double pl = std::max(p, q), ql = std::min(p, q);
+      kstats[0] += 1;
+      kstats[1] += 4.0 * (6.0 * pl * ql * ql + 20.0 * ql * ql * ql);
+      kstats[2] += fms;
+    }
     if (rank_rec) rank_rec->push_back(h.kept | (pass2 ? (1 << kPass2Bit) : 0));
     if (tape) {
       FactRec& f = last_fact;
@@ -341,13 +361,42 @@ struct gcamps_ctx {
     phase_apply(P, phi);
   }
 
+  // Timing of one gate's MPO launches: events recorded around them and read once they have
+  // completed (the compression that follows synchronises the stream).
+  void settle_mpo() {
+    if (!mpo_pending) return;
+    GC_HIP(hipEventSynchronize(evm1));
+    float ms = 0.0f;
+    GC_HIP(hipEventElapsedTime(&ms, evm0, evm1));
+    kstats[5] += ms;
+    mpo_pending = false;
+  }
+  void mpo_begin() {
+    settle_mpo();
+    GC_HIP(hipEventRecord(evm0, stream));
+  }
+  void mpo_end() {
+    GC_HIP(hipEventRecord(evm1, stream));
+    mpo_pending = true;
+  }
+  // Algorithmic bytes of one MPO site launch of bond J on [l, r]: the site tensor read once and
+  // its product (bonds multiplied by J inside the support) written once, complex128.
+  void mpo_count(int i, int l, int r, int J) {
+    const double in = (double)chi[i] * d * chi[i + 1];
+    const double out = (double)chi[i] * (i > l ? J : 1) * d * chi[i + 1] * (i < r ? J : 1);
+    kstats[3] += 1;
+    kstats[4] += 16.0 * (in + out);
+  }
+
   // Apply sum_b c_b P^b (P from the tableau) to the MPS and compress.
   void phase_apply(const GateRec& P, const double* phi) {
     const int l = P.l, r = P.r;
     const MpoCoeff co = mpo_coeff(P, phi);
     move_centre(l);
+    mpo_begin();
     for (int i = l; i <= r; ++i) {
       int kind = (l == r) ? 3 : (i == l ? 0 : (i == r ? 2 : 1));
+      mpo_count(i, l, r, d);
       if (tape) {
         TapeOp op;
         op.kind = TAPE_MPO;
@@ -367,6 +416,7 @@ struct gcamps_ctx {
       launch_mpo_site(stream, kind, d, chi[i], chi[i + 1], P.x[i], P.z[i], co, site[i], spare);
       std::swap(site[i], spare);
     }
+    mpo_end();
     for (int j = l + 1; j <= r; ++j) chi[j] *= d;
     compress(l, r);
     gates += 1;
@@ -472,15 +522,18 @@ struct gcamps_ctx {
       tm.coef[j] = z64{cj.real(), cj.imag()};
     }
     move_centre(l);
+    mpo_begin();
     for (int i = l; i <= r; ++i) {
       const int kind = (l == r) ? 3 : (i == l ? 0 : (i == r ? 2 : 1));
       for (int j = 0; j < J; ++j) {
         tm.x[j] = P[j].x[i];
         tm.z[j] = P[j].z[i];
       }
+      mpo_count(i, l, r, J);
       launch_mpo_sum_site(stream, kind, d, J, chi[i], chi[i + 1], tm, site[i], spare);
       std::swap(site[i], spare);
     }
+    mpo_end();
     for (int j = l + 1; j <= r; ++j) chi[j] *= J;
     compress(l, r);
     gates += 1;

@@ -30,6 +30,7 @@ SYMBOLS = [
     "gcamps_factorize", "gcamps_disentangle", "gcamps_expectation",
     "gcamps_statevector", "gcamps_amplitude", "gcamps_get_tableau", "gcamps_get_bond_dims",
     "gcamps_get_fidelity", "gcamps_get_choice_log", "gcamps_get_site", "gcamps_get_stats",
+    "gcamps_get_kernel_stats",
     "gcamps_batch_workspace_bytes", "gcamps_batch_run", "gcamps_grad_record", "gcamps_grad_loss",
     "gcamps_grad_gradient", "gcamps_grad_stats", "gcamps_grad_destroy", "gcamps_last_error",
 ]
@@ -108,6 +109,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gcamps_get_choice_log": [P, C.POINTER(I32), I64, C.POINTER(I64)],
         "gcamps_get_site": [P, I32, C.POINTER(D), I64, C.POINTER(I32)],
         "gcamps_get_stats": [P, C.POINTER(D)],
+        "gcamps_get_kernel_stats": [P, C.POINTER(D)],
         "gcamps_batch_workspace_bytes": [C.POINTER(CBatchItem), I32, I32, C.POINTER(SZ)],
         "gcamps_batch_run": [C.POINTER(CBatchItem), I32, P, I32, P, SZ, C.POINTER(D)],
         "gcamps_grad_record": [C.POINTER(Config), C.POINTER(COp), I64, C.POINTER(I32), C.POINTER(D), I32, P, P,
@@ -349,6 +351,13 @@ class State:
         _check(lib().gcamps_get_site(self.handle, i, buf, cnt, dims))
         v = np.frombuffer(buf, dtype=np.float64)
         return (v[0::2] + 1j * v[1::2]).reshape(dims[0], dims[1], dims[2])
+
+    def kernel_stats(self) -> dict:
+        """Compression and MPO counters (gcamps_get_kernel_stats)."""
+        out = (C.c_double * 8)()
+        _check(lib().gcamps_get_kernel_stats(self.handle, out))
+        keys = ["factorisations", "factor_svd_flops", "factor_ms", "mpo_launches", "mpo_bytes", "mpo_ms"]
+        return dict(zip(keys, list(out)))
 
     def stats(self) -> dict:
         out = (C.c_double * 16)()
