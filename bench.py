@@ -217,7 +217,7 @@ def main_batch(args):
     if st["tiled_launches"] > 0 and st["tiled_ms"] > 0:
         achieved = st["tiled_flops"] / (st["tiled_ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None, "kernel": "k_gram_purity<float, 4, 8>",
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None, "kernel": "k_gram_purity_dl",
                 "launches": int(st["tiled_launches"]), "avg_ms": st["tiled_ms"] / st["tiled_launches"]}
     cpu = None if args.no_cpu else batch_cpu_baseline(bw, args.cpu_budget)
     fids = [r["fidelity"] for r in res]
@@ -724,7 +724,7 @@ def main():
                 "frac": achieved / peak, "traffic": None if bf else measured_traffic(),
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE, copy-calibrated)",
                 "algorithmic_bytes": s32["tiled_bytes"] / s32["tiled_launches"],
-                "kernel": "k_gram_purity_bf16" if bf else "k_gram_purity<float, 4, 8>",
+                "kernel": "k_gram_purity_bf16" if bf else "k_gram_purity_dl",
                 "launches": int(s32["tiled_launches"]), "avg_ms": per_launch_ms}
         if bf:
             roof["note"] = ("algorithmic flops (4 m^2 k per candidate); the split form issues three BF16 "
