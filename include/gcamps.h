@@ -260,10 +260,8 @@ int32_t gcamps_get_site(gcamps_ctx* ctx, int32_t site, double* out, int64_t cap,
  * replica mode: 4 (X d^2)^2 Y + 8 X (X + 1) / 2 d^8 + 2 N_c d^8 with X, Y the smaller and larger bond), [5] algorithmic flops of the Gram products of
  * the factorisations, [6] full-set scoring kernel time in ms (device events), [7] total time
  * inside gcamps_* calls in ms (host clock), [8] flops of the FP64 window re-score, [9] its
- * kernel time in ms, [10] scoring calls (bonds x passes), [11] launches of the main Gram-purity
- * MFMA kernel of the scoring precision (full-set scoring; in FP32 mode the direct-to-LDS kernel,
- * which runs when the larger side k of the two-site matrix is a multiple of 16, so other shapes
- * are not counted), [12] their summed kernel time in ms (device events around each
+ * kernel time in ms, [10] scoring calls (bonds x passes), [11] launches of the Gram-purity MFMA
+ * kernel (full-set scoring), [12] their summed kernel time in ms (device events around each
  * launch), [13] their algorithmic flops (4 m^2 k per candidate), [14] bond splits that factorised only the
  * centre tensor (identity kept), [15] algorithmic bytes read by the Gram-purity launches (each
  * rotated m x k matrix once). */

@@ -73,9 +73,7 @@ void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* s
 // overrides `count` (the list length is then only known on the device).  partial: scratch of
 // count * tiles doubles for the tiled path; nbuf: scratch for the rotated matrices of a chunk
 // of candidates (the tiled path processes as many candidates per launch as fit).  evs: optional
-// event pairs recorded around each launch of the precision's main Gram-purity kernel (count
-// returned in *evused); in FP32 that is k_gram_purity_dl, so shapes whose larger side is not a
-// multiple of 16 record none.
+// event pairs recorded around each Gram-purity launch (count returned in *evused).
 void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64* theta,
                   const z64* q64, const c32* q32, const int* cand_list, int count,
                   const int* nlimit, double* s2, double* partial, size_t partial_cap, void* nbuf,

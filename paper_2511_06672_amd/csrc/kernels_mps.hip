@@ -280,14 +280,15 @@ __device__ __forceinline__ void tile_pair(int idx, int nt, int& I, int& J) {
   J = i + rem;
 }
 
-// Rotated two-site matrices N_c (m x k, row-major) for a chunk of candidates.  One thread per
-// (a, b) loads Theta(a, :, :, b) once and writes the d^2 entries (Q_c Theta)(a, s1', s2', b) to
-// their (row, col) positions: rows (a s1'), cols (s2' b) when chil*d <= d*chir, else transposed.
+// Rotated two-site matrices N_c (m x k, row-major, leading dimension ldk >= k) for a chunk of
+// candidates.  One thread per (a, b) loads Theta(a, :, :, b) once and writes the d^2 entries
+// (Q_c Theta)(a, s1', s2', b) to their (row, col) positions: rows (a s1'), cols (s2' b) when
+// chil*d <= d*chir, else transposed.  Columns k..ldk-1 of every row are written as zeros.
 template <typename T, int DD>
 __global__ __launch_bounds__(256) void k_gen_rotated(int d_rt, int chil, int chir, const z64* __restrict__ theta,
                                                      const cx<T>* __restrict__ qall, const int* __restrict__ list,
                                                      int c0, int cnt, const int* __restrict__ nlimit,
-                                                     cx<T>* __restrict__ out, size_t stride) {
+                                                     cx<T>* __restrict__ out, size_t stride, int ldk) {
   // DD > 0: qudit dimension fixed at compile time (the d^2-vector stays in registers)
   const int d = DD > 0 ? DD : d_rt;
   constexpr int VMAX = DD > 0 ? DD * DD : kMaxD * kMaxD;
@@ -298,6 +299,12 @@ __global__ __launch_bounds__(256) void k_gen_rotated(int d_rt, int chil, int chi
   const bool rows_first = chil * d <= d * chir;
   const int k = rows_first ? d * chir : chil * d;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  cx<T>* o = out + (size_t)ls * stride;
+  if (ldk > k) {
+    const int pad = ldk - k, m = rows_first ? chil * d : d * chir;
+    const size_t np = (size_t)m * pad, nth = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = idx; e < np; e += nth) o[(e / pad) * ldk + k + e % pad] = cx<T>{T(0), T(0)};
+  }
   if (idx >= (size_t)chil * chir) return;
   // rows_first: b fastest (contiguous columns s2'*chir + b); otherwise a fastest
   int a, b;
@@ -318,7 +325,6 @@ __global__ __launch_bounds__(256) void k_gen_rotated(int d_rt, int chil, int chi
     const z64 tv = th[(size_t)x * chir];
     v[x] = cx<T>{T(tv.re), T(tv.im)};
   }
-  cx<T>* o = out + (size_t)ls * stride;
   for (int y = 0; y < D2; ++y) {
     const int s1p = y / d, s2p = y - s1p * d;
     cx<T> acc = {T(0), T(0)};
@@ -329,21 +335,20 @@ __global__ __launch_bounds__(256) void k_gen_rotated(int d_rt, int chil, int chi
     }
     const size_t row = rows_first ? (size_t)a * d + s1p : (size_t)s2p * chir + b;
     const size_t col = rows_first ? (size_t)s2p * chir + b : (size_t)a * d + s1p;
-    o[row * k + col] = acc;
+    o[row * ldk + col] = acc;
   }
 }
 
-// Purity tiles: for candidate slot `ls` of the chunk, tile (I, J), I <= J, of rho = N N^H over the
-// k columns, on MFMA (16x16x4, FP32 or FP64 accumulate).  The NW waves form two rows of NW / 2:
-// each owns BL x (2 BL / (NW / 2)) 16x16 blocks of the TT x TT tile (TT = 32 * BL).  The FP32
-// instance uses three real products per complex product and runs eight waves, one workgroup per
-// CU: two waves per SIMD, so one wave's LDS waits overlap the other's MFMAs (7% faster than four
-// waves holding the whole register file); it serves the shapes whose k is not a multiple of 16
-// (k_gram_purity_dl below takes the others).  The FP64 instance (window re-score) uses four
-// products and four waves, two workgroups per CU.  The epilogue writes sum |rho_tile|^2 (doubled
-// off the diagonal) and the tile's trace to partial[slot][tile].
+// Purity tiles in FP64 (window re-score): for candidate slot `ls` of the chunk, tile (I, J),
+// I <= J, of rho = N N^H over the k columns, on MFMA (16x16x4 FP64), four real products per
+// complex product.  The NW waves form two rows of NW / 2: each owns BL x (2 BL / (NW / 2))
+// 16x16 blocks of the TT x TT tile (TT = 32 * BL); instantiated with four waves, two workgroups
+// per CU.  Operands are staged through registers: chunk c + 1 is fetched while chunk c is
+// multiplied, then transposed into LDS (re and im planes, k-major).  The FP32 path uses
+// k_gram_purity_dl below.  The epilogue writes sum |rho_tile|^2 (doubled off the diagonal) and
+// the tile's trace to partial[slot][tile].
 template <typename T, int BL, int NW>
-__global__ __launch_bounds__(64 * NW, (std::is_same<T, float>::value ? 1 : 2)) void k_gram_purity(int m, int k, const cx<T>* __restrict__ nbase, size_t stride,
+__global__ __launch_bounds__(64 * NW, 2) void k_gram_purity(int m, int k, const cx<T>* __restrict__ nbase, size_t stride,
                                                      int c0, int cnt, const int* __restrict__ nlimit, int ntp,
                                                      double* __restrict__ partial) {
   typedef typename AccT<T>::type acc_t;
@@ -370,16 +375,13 @@ __global__ __launch_bounds__(64 * NW, (std::is_same<T, float>::value ? 1 : 2)) v
   __shared__ double red[NT];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w / WC) * (TT / 2), wc = (w % WC) * (TT / WC);
-  // FP32: three real products per complex product, T1 = Ar Br^T, T2 = Ai Bi^T (B holds -Im),
-  // T3 = (Ar + Ai)(Br + Bi)^T; re = T1 - T2, im = T3 - T1 - T2.  FP64: re and im directly.
-  constexpr bool k3 = std::is_same<T, float>::value;
-  acc_t accr[BLR][BLC], acci[BLR][BLC], acc3[k3 ? BLR : 1][k3 ? BLC : 1];
+  // re and im accumulated directly (B holds -Im)
+  acc_t accr[BLR][BLC], acci[BLR][BLC];
   for (int i = 0; i < BLR; ++i)
     for (int j = 0; j < BLC; ++j)
       for (int q = 0; q < 4; ++q) {
         accr[i][j][q] = T(0);
         acci[i][j][q] = T(0);
-        if constexpr (k3) acc3[i][j][q] = T(0);
       }
   const int r0 = I * TT, q0 = J * TT;
   constexpr int U = TT * KC / NT;
@@ -428,25 +430,13 @@ __global__ __launch_bounds__(64 * NW, (std::is_same<T, float>::value ? 1 : 2)) v
         br[j] = Bs[sg][0][ka][wc + j * 16 + (lane & 15)];
         bi[j] = Bs[sg][1][ka][wc + j * 16 + (lane & 15)];
       }
-      if constexpr (k3) {
-        T sa[BLR], sb[BLC];
-        for (int i = 0; i < BLR; ++i) sa[i] = ar[i] + ai[i];
-        for (int j = 0; j < BLC; ++j) sb[j] = br[j] + bi[j];
-        for (int i = 0; i < BLR; ++i)
-          for (int j = 0; j < BLC; ++j) {
-            accr[i][j] = mfma_t(ar[i], br[j], accr[i][j]);   // T1
-            acci[i][j] = mfma_t(ai[i], bi[j], acci[i][j]);   // T2
-            acc3[i][j] = mfma_t(sa[i], sb[j], acc3[i][j]);   // T3
-          }
-      } else {
-        for (int i = 0; i < BLR; ++i)
-          for (int j = 0; j < BLC; ++j) {
-            accr[i][j] = mfma_t(ar[i], br[j], accr[i][j]);
-            accr[i][j] = mfma_t(-ai[i], bi[j], accr[i][j]);
-            acci[i][j] = mfma_t(ar[i], bi[j], acci[i][j]);
-            acci[i][j] = mfma_t(ai[i], br[j], acci[i][j]);
-          }
-      }
+      for (int i = 0; i < BLR; ++i)
+        for (int j = 0; j < BLC; ++j) {
+          accr[i][j] = mfma_t(ar[i], br[j], accr[i][j]);
+          accr[i][j] = mfma_t(-ai[i], bi[j], accr[i][j]);
+          acci[i][j] = mfma_t(ar[i], bi[j], acci[i][j]);
+          acci[i][j] = mfma_t(ai[i], br[j], acci[i][j]);
+        }
     }
     if (more) stash(sg ^ 1);
     __syncthreads();
@@ -460,15 +450,7 @@ __global__ __launch_bounds__(64 * NW, (std::is_same<T, float>::value ? 1 : 2)) v
         const int row = r0 + wr + i * 16 + mfma_row<T>(lane, q);
         const int col = q0 + wc + j * 16 + (lane & 15);
         if (row < m && col < m) {
-          double re, im;
-          if constexpr (k3) {
-            const double t1 = (double)accr[i][j][q], t2 = (double)acci[i][j][q], t3 = (double)acc3[i][j][q];
-            re = t1 - t2;
-            im = t3 - t1 - t2;
-          } else {
-            re = (double)accr[i][j][q];
-            im = (double)acci[i][j][q];
-          }
+          const double re = (double)accr[i][j][q], im = (double)acci[i][j][q];
           pur += wgt * (re * re + im * im);
           if (I == J && row == col) tr += re;
         }
@@ -553,19 +535,24 @@ __global__ __launch_bounds__(256) void k_gen_rotated_bf16(int d_rt, int chil, in
   }
 }
 
-// FP32 Gram purity with direct-to-LDS operand loads, for k % 16 == 0; the same tiles, waves,
-// three-product form, XCD-aware order and epilogue as k_gram_purity<float, 4, 8>.  With k a
-// multiple of 16 every 16-column chunk of every row is eight aligned 16-byte units (two complex
-// values each), so the chunk of an operand tile (128 rows) is 16 blocks of 8 rows x 8 units, and
-// one global_load_lds_dwordx4 of a wave moves a block straight into LDS, lane l filling the l-th
+// FP32 Gram purity with direct-to-LDS operand loads.  The rotated matrices arrive with rows
+// padded by zero columns to a multiple of 16 (the zeros add nothing to rho), so k % 16 == 0.
+// 128 x 128 tiles in eight waves (two rows of four, 64 x 32 each: two waves per SIMD, so one
+// wave's LDS waits overlap the other's MFMAs); XCD-aware order and epilogue as in
+// k_gram_purity.  Three real products per complex product (a quarter fewer MFMAs than four):
+// T1 = Ar Br^T, T2 = Ai Bi^T with Bi = -Im B, T3 = (Ar + Ai)(Br + Bi)^T; re = T1 - T2,
+// im = T3 - T1 - T2.
+// Every 16-column chunk of a row is eight aligned 16-byte units (two complex values each), so
+// the chunk of an operand tile (128 rows) is 16 blocks of 8 rows x 8 units, and one
+// global_load_lds_dwordx4 of a wave moves a block straight into LDS, lane l filling the l-th
 // 16-byte slot.  Lane l loads row 8b + (l >> 3), unit (l & 7) ^ (l >> 3): the units of a row are
 // XOR-swizzled across its block so that the 16 rows read by one MFMA lane group fall in distinct
 // banks.  Rows at or beyond m read row m - 1 (they only feed products outside the m x m result,
 // which the epilogue drops).  The k order inside a chunk is permuted the same way for both
 // operands: at MFMA step s lane group g takes k = 4g + s, so a lane reads its four k values of a
 // row as two 16-byte units.  The next chunk streams into the other LDS stage while this one is
-// multiplied: no register staging, one wait and one barrier per chunk.  (The register-staged
-// kernel peaked at 121 TFLOP/s at m = k = 768, this one at 140.)
+// multiplied: no register staging, one wait and one barrier per chunk.  (Staging through
+// registers, as k_gram_purity does, peaked at 121 TFLOP/s at m = k = 768; this kernel at 140.)
 __device__ __forceinline__ int dl_slot(int r, int ku) { return (r >> 3) * 64 + ((r & 7) << 3) + (ku ^ (r & 7)); }
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -605,7 +592,6 @@ __global__ __launch_bounds__(512, 1) void k_gram_purity_dl(int m, int k, const c
         acc3[i][j][q] = 0.f;
       }
   const int g = lane >> 4, rl = lane & 15;
-  // T1 = Ar Br^T, T2 = Ai Bi^T with Bi = -Im B, T3 = (Ar + Ai)(Br + Bi)^T, as in k_gram_purity
   auto compute = [&](const float4* As, const float4* Bs) {
     float ar[BLR][4], ai[BLR][4], br[BLC][4], bi[BLC][4];
 #pragma unroll
@@ -1114,7 +1100,9 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
   const int ntp = nt * (nt + 1) / 2;
   GC_CHECK((size_t)count * ntp * 2 <= partial_cap, GCAMPS_ECAPACITY, "scoring partial buffer too small");
   const size_t elem = (prec == GCAMPS_SCORE_FP64) ? sizeof(z64) : sizeof(c32);
-  const size_t stride = (size_t)m * k;
+  // FP32 rows are padded with zero columns to a multiple of 16 for k_gram_purity_dl
+  const int ldk = (prec == GCAMPS_SCORE_FP64) ? k : (k + 15) / 16 * 16;
+  const size_t stride = (size_t)m * ldk;
   const int chunk = (int)std::min<size_t>((size_t)count, nbuf_bytes / (stride * elem));
   GC_CHECK(chunk >= 1, GCAMPS_ECAPACITY, "rotated-matrix buffer too small");
   const dim3 ggen(blocks_for((size_t)chil * chir, 256), chunk);
@@ -1126,13 +1114,13 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
       z64* nb = reinterpret_cast<z64*>(nbuf);
       if (d == 3)
         hipLaunchKernelGGL((k_gen_rotated<double, 3>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
-                           nlimit, nb, stride);
+                           nlimit, nb, stride, ldk);
       else if (d == 2)
         hipLaunchKernelGGL((k_gen_rotated<double, 2>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
-                           nlimit, nb, stride);
+                           nlimit, nb, stride, ldk);
       else
         hipLaunchKernelGGL((k_gen_rotated<double, 0>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
-                           nlimit, nb, stride);
+                           nlimit, nb, stride, ldk);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
       hipLaunchKernelGGL((k_gram_purity<double, 2, 4>), gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
                          partial);
@@ -1141,23 +1129,16 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
       c32* nb = reinterpret_cast<c32*>(nbuf);
       if (d == 3)
         hipLaunchKernelGGL((k_gen_rotated<float, 3>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride);
+                           nlimit, nb, stride, ldk);
       else if (d == 2)
         hipLaunchKernelGGL((k_gen_rotated<float, 2>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride);
+                           nlimit, nb, stride, ldk);
       else
         hipLaunchKernelGGL((k_gen_rotated<float, 0>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride);
-      if (k % 16 == 0) {
-        if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
-        hipLaunchKernelGGL(k_gram_purity_dl, gp, dim3(512), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp, partial);
-        if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
-      } else {  // not timed: the events cover the FP32 path's main kernel only
-        hipLaunchKernelGGL((k_gram_purity<float, 4, 8>), gp, dim3(512), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
-                           partial);
-        GC_LAUNCH_CHECK();
-        continue;
-      }
+                           nlimit, nb, stride, ldk);
+      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
+      hipLaunchKernelGGL(k_gram_purity_dl, gp, dim3(512), 0, s, m, ldk, nb, stride, c0, cnt, nlimit, ntp, partial);
+      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
     }
     GC_LAUNCH_CHECK();
     if (ev >= 0) ++(*evused);
