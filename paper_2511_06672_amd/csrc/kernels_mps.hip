@@ -479,12 +479,13 @@ __device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
 }
 
 // M_c = reshape(Q_c Theta) (as k_gen_rotated<float>) written as planes [Re hi, Re lo, Im hi, Im lo],
-// each m x k row-major BF16; candidate slot ls at out + ls * stride (stride = 4 m k elements).
+// each m x k row-major BF16 with leading dimension ldk >= k (columns k..ldk-1 written as zeros);
+// candidate slot ls at out + ls * stride (stride = 4 m ldk elements).
 template <int DD>
 __global__ __launch_bounds__(256) void k_gen_rotated_bf16(int d_rt, int chil, int chir, const z64* __restrict__ theta,
                                                           const c32* __restrict__ qall, const int* __restrict__ list,
                                                           int c0, int cnt, const int* __restrict__ nlimit,
-                                                          __bf16* __restrict__ out, size_t stride) {
+                                                          __bf16* __restrict__ out, size_t stride, int ldk) {
   const int d = DD > 0 ? DD : d_rt;
   constexpr int VMAX = DD > 0 ? DD * DD : kMaxD * kMaxD;
   const int ls = blockIdx.y;
@@ -495,6 +496,16 @@ __global__ __launch_bounds__(256) void k_gen_rotated_bf16(int d_rt, int chil, in
   const int k = rows_first ? d * chir : chil * d;
   const int m = rows_first ? chil * d : d * chir;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __bf16* o = out + (size_t)ls * stride;
+  const size_t plane = (size_t)m * ldk;
+  if (ldk > k) {  // zero pad columns k..ldk-1 of every row of the four planes
+    const int pad = ldk - k;
+    const size_t np = (size_t)m * pad, nth = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = idx; e < np; e += nth) {
+      const size_t at = (e / pad) * ldk + k + e % pad;
+      for (int pl = 0; pl < 4; ++pl) o[pl * plane + at] = (__bf16)0.f;
+    }
+  }
   if (idx >= (size_t)chil * chir) return;
   int a, b;
   if (rows_first) {
@@ -514,8 +525,6 @@ __global__ __launch_bounds__(256) void k_gen_rotated_bf16(int d_rt, int chil, in
     const z64 tv = th[(size_t)x * chir];
     v[x] = c32{(float)tv.re, (float)tv.im};
   }
-  __bf16* o = out + (size_t)ls * stride;
-  const size_t plane = (size_t)m * k;
   for (int y = 0; y < D2; ++y) {
     const int s1p = y / d, s2p = y - s1p * d;
     c32 acc = {0.f, 0.f};
@@ -526,7 +535,7 @@ __global__ __launch_bounds__(256) void k_gen_rotated_bf16(int d_rt, int chil, in
     }
     const size_t row = rows_first ? (size_t)a * d + s1p : (size_t)s2p * chir + b;
     const size_t col = rows_first ? (size_t)s2p * chir + b : (size_t)a * d + s1p;
-    const size_t e = row * k + col;
+    const size_t e = row * ldk + col;
     const __bf16 rh = (__bf16)acc.re, ih = (__bf16)acc.im;
     o[e] = rh;
     o[plane + e] = (__bf16)(acc.re - (float)rh);
@@ -688,9 +697,14 @@ __global__ __launch_bounds__(512, 1) void k_gram_purity_dl(int m, int k, const c
 // tile J (same layout, rho[r][c] = sum_k M[r][k] conj(M[c][k])):
 //   Re rho += Rh Rh + Rh Rl + Rl Rh + Ih Ih + Ih Il + Il Ih
 //   Im rho += Ih Rh + Ih Rl + Il Rh - Rh Ih - Rh Il - Rl Ih.
-// LDS rows are 64 bytes (4 groups of 8 k); group g of row r sits in slot g ^ ((r >> 2) & 3), so
-// the 16 rows read by a quarter-wave hit disjoint banks.  Two stages, one barrier per chunk,
-// XCD-aware workgroup order as in k_gram_purity.
+// The planes arrive with rows padded by zero columns to a multiple of 32, so k % 32 == 0 and
+// every chunk of a row is four aligned 16-byte groups.  LDS rows are 64 bytes; group g of row r
+// sits in slot g ^ ((r >> 2) & 3), so the 16 rows read by a quarter-wave hit disjoint banks.
+// Chunks are loaded straight into LDS: wave w moves plane w of each panel, one
+// global_load_lds_dwordx4 per 16 rows (lane l fills the l-th 16-byte slot: row l >> 2, slot
+// l & 3), and the next chunk streams into the other stage while this one is multiplied (one
+// wait and one barrier per chunk).  Rows at or beyond m read row m - 1; they only feed results
+// outside the m x m Gram.  XCD-aware workgroup order as in k_gram_purity.
 constexpr int BT = 128, BKC = 32;
 __global__ __launch_bounds__(256) void k_gram_purity_bf16(int m, int k, const __bf16* __restrict__ nbase,
                                                           size_t stride, int c0, int cnt,
@@ -708,8 +722,9 @@ __global__ __launch_bounds__(256) void k_gram_purity_bf16(int m, int k, const __
   int I, J;
   tile_pair(tile, nt, I, J);
   const bool diag = (I == J);
-  // [stage][panel A/B][plane][row][32 k] as 16-byte groups
-  __shared__ us8 lds[2][2][4][BT][4];
+  // two stages of [panel A/B][plane][row][32 k as four 16-byte groups]
+  __shared__ us8 S0[2][4][BT][4];
+  __shared__ us8 S1[2][4][BT][4];
   __shared__ double red[256];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * (BT / 2), wc = (w & 1) * (BT / 2);
@@ -721,64 +736,43 @@ __global__ __launch_bounds__(256) void k_gram_purity_bf16(int m, int k, const __
         acci[i][j][q] = 0.f;
       }
   const int r0 = I * BT, q0 = J * BT;
-  const bool kvec = (k % 8) == 0;  // 16-byte aligned groups
-  // per chunk and panel: 4 planes x 128 rows x 4 groups = 2048 groups, 8 per thread
-  us8 pa[8], pb[8];
-  auto fetch_panel = [&](int base_row, int k0, us8* dst) {
+  // loader lane: row (lane >> 2) of a 16-row block, slot lane & 3 holding group slot ^ ((row >> 2) & 3)
+  const int lrow = lane >> 2, lgrp = (lane & 3) ^ ((lrow >> 2) & 3);
+  const __bf16* pA = N + (size_t)w * plane + 8 * lgrp;
+  auto issue = [&](us8 (*Sx)[4][BT][4], int k0) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int e = t + 256 * u;
-      const int pl = e >> 9, row = (e >> 2) & 127, g = e & 3;
-      const int gr = base_row + row, gk = k0 + 8 * g;
-      us8 v = (us8)(unsigned short)0;
-      if (gr < m) {
-        const __bf16* src = N + pl * plane + (size_t)gr * k + gk;
-        if (kvec && gk + 8 <= k) {
-          v = *reinterpret_cast<const us8*>(src);
-        } else {
-          for (int x = 0; x < 8; ++x)
-            if (gk + x < k) v[x] = __builtin_bit_cast(unsigned short, src[x]);
-        }
-      }
-      dst[u] = v;
+      const int row = 16 * u + lrow;
+      __builtin_amdgcn_global_load_lds((const void*)(pA + (size_t)min(r0 + row, m - 1) * k + k0),
+                                       (lds_void*)&Sx[0][w][16 * u][0], 16, 0, 0);
+      if (!diag)
+        __builtin_amdgcn_global_load_lds((const void*)(pA + (size_t)min(q0 + row, m - 1) * k + k0),
+                                         (lds_void*)&Sx[1][w][16 * u][0], 16, 0, 0);
     }
+    __builtin_amdgcn_sched_barrier(0);
   };
-  auto stash_panel = [&](int sg, int panel, const us8* src) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = t + 256 * u;
-      const int pl = e >> 9, row = (e >> 2) & 127, g = e & 3;
-      lds[sg][panel][pl][row][g ^ ((row >> 2) & 3)] = src[u];
-    }
+  auto settle = [&]() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads have landed in LDS
+    __syncthreads();                // ... and every other wave's
   };
-  fetch_panel(r0, 0, pa);
-  if (!diag) fetch_panel(q0, 0, pb);
-  stash_panel(0, 0, pa);
-  if (!diag) stash_panel(0, 1, pb);
-  __syncthreads();
   const int bpan = diag ? 0 : 1;
   const int g = lane >> 4, rr = lane & 15;
-  int sg = 0;
-  for (int k0 = 0; k0 < k; k0 += BKC) {
-    const bool more = k0 + BKC < k;
-    if (more) {
-      fetch_panel(r0, k0 + BKC, pa);
-      if (!diag) fetch_panel(q0, k0 + BKC, pb);
-    }
+  auto compute = [&](us8 (*Sx)[4][BT][4]) {
     bf8 A[4][6], B[4][4];  // A: [block i][Rh, Rl, Ih, Il, -Rh, -Rl]; B: [block j][Rh, Rl, Ih, Il]
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = wc + j * 16 + rr;
       const int slotg = g ^ ((row >> 2) & 3);
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) B[j][pl] = __builtin_bit_cast(bf8, lds[sg][bpan][pl][row][slotg]);
+      for (int pl = 0; pl < 4; ++pl) B[j][pl] = __builtin_bit_cast(bf8, Sx[bpan][pl][row][slotg]);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = wr + i * 16 + rr;
       const int slotg = g ^ ((row >> 2) & 3);
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) A[i][pl] = __builtin_bit_cast(bf8, lds[sg][0][pl][row][slotg]);
+      for (int pl = 0; pl < 4; ++pl) A[i][pl] = __builtin_bit_cast(bf8, Sx[0][pl][row][slotg]);
       A[i][4] = bf8_neg(A[i][0]);
       A[i][5] = bf8_neg(A[i][1]);
     }
@@ -797,13 +791,20 @@ __global__ __launch_bounds__(256) void k_gram_purity_bf16(int m, int k, const __
             acci[i][j] = mfma_bf(A[i][TA[term]], B[j][TB[term]], acci[i][j]);
         }
     }
-    if (more) {
-      stash_panel(sg ^ 1, 0, pa);
-      if (!diag) stash_panel(sg ^ 1, 1, pb);
-    }
-    __syncthreads();
-    sg ^= 1;
+  };
+  const int nch = k / BKC;
+  issue(S0, 0);
+  settle();
+  int c = 0;
+  for (; c + 2 <= nch; c += 2) {
+    issue(S1, (c + 1) * BKC);
+    compute(S0);
+    settle();
+    if (c + 2 < nch) issue(S0, (c + 2) * BKC);
+    compute(S1);
+    settle();
   }
+  if (c < nch) compute(S0);
   double pur = 0.0, tr = 0.0;
   const double wgt = diag ? 1.0 : 2.0;
   for (int i = 0; i < 4; ++i)
@@ -1068,7 +1069,8 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
     const int nt = (m + BT - 1) / BT;
     const int ntp = nt * (nt + 1) / 2;
     GC_CHECK((size_t)count * ntp * 2 <= partial_cap, GCAMPS_ECAPACITY, "scoring partial buffer too small");
-    const size_t stride = 4 * (size_t)m * k;  // BF16 elements per candidate (four planes)
+    const int ldk = (k + BKC - 1) / BKC * BKC;  // rows padded with zeros to whole 32-column chunks
+    const size_t stride = 4 * (size_t)m * ldk;  // BF16 elements per candidate (four planes)
     const int chunk = (int)std::min<size_t>((size_t)count, nbuf_bytes / (stride * sizeof(__bf16)));
     GC_CHECK(chunk >= 1, GCAMPS_ECAPACITY, "rotated-matrix buffer too small");
     __bf16* nb = reinterpret_cast<__bf16*>(nbuf);
@@ -1078,15 +1080,15 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
       const int ev = (evs && evused && 2 * (*evused) + 1 < evcap) ? 2 * (*evused) : -1;
       if (d == 3)
         hipLaunchKernelGGL((k_gen_rotated_bf16<3>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride);
+                           nlimit, nb, stride, ldk);
       else if (d == 2)
         hipLaunchKernelGGL((k_gen_rotated_bf16<2>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride);
+                           nlimit, nb, stride, ldk);
       else
         hipLaunchKernelGGL((k_gen_rotated_bf16<0>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride);
+                           nlimit, nb, stride, ldk);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
-      hipLaunchKernelGGL(k_gram_purity_bf16, gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp, partial);
+      hipLaunchKernelGGL(k_gram_purity_bf16, gp, dim3(256), 0, s, m, ldk, nb, stride, c0, cnt, nlimit, ntp, partial);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
       GC_LAUNCH_CHECK();
       if (ev >= 0) ++(*evused);
