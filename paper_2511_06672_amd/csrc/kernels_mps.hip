@@ -280,62 +280,79 @@ __device__ __forceinline__ void tile_pair(int idx, int nt, int& I, int& J) {
   J = i + rem;
 }
 
+// Candidates per generator thread: kGenCands for chunks of at least kGenMinChunk candidates,
+// else one.  Lists whose length is only known on the device (the window re-score) take one too:
+// they are usually short, and a few candidates need every block they can get.
+constexpr int kGenCands = 8, kGenMinChunk = 64;
+
 // Rotated two-site matrices N_c (m x k, row-major, leading dimension ldk >= k) for a chunk of
 // candidates.  One thread per (a, b) loads Theta(a, :, :, b) once and writes the d^2 entries
 // (Q_c Theta)(a, s1', s2', b) to their (row, col) positions: rows (a s1'), cols (s2' b) when
-// chil*d <= d*chir, else transposed.  Columns k..ldk-1 of every row are written as zeros.
+// chil*d <= d*chir, else transposed.  Columns k..ldk-1 of every row are written as zeros.  A
+// thread serves cpt consecutive candidates of the chunk (blockIdx.y picks the group), so Theta
+// is read once per group rather than once per candidate.
 template <typename T, int DD>
 __global__ __launch_bounds__(256) void k_gen_rotated(int d_rt, int chil, int chir, const z64* __restrict__ theta,
                                                      const cx<T>* __restrict__ qall, const int* __restrict__ list,
                                                      int c0, int cnt, const int* __restrict__ nlimit,
-                                                     cx<T>* __restrict__ out, size_t stride, int ldk) {
+                                                     cx<T>* __restrict__ out, size_t stride, int ldk, int cpt) {
   // DD > 0: qudit dimension fixed at compile time (the d^2-vector stays in registers)
   const int d = DD > 0 ? DD : d_rt;
   constexpr int VMAX = DD > 0 ? DD * DD : kMaxD * kMaxD;
-  const int ls = blockIdx.y;
-  const int slot = c0 + ls;
-  if (ls >= cnt || (nlimit && slot >= *nlimit)) return;
-  const int c = list ? list[slot] : slot;
   const bool rows_first = chil * d <= d * chir;
   const int k = rows_first ? d * chir : chil * d;
+  const int m = rows_first ? chil * d : d * chir;
+  const int g0 = blockIdx.y * cpt;  // first candidate of this block's group
+  if (g0 >= cnt || (nlimit && c0 + g0 >= *nlimit)) return;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  cx<T>* o = out + (size_t)ls * stride;
-  if (ldk > k) {
-    const int pad = ldk - k, m = rows_first ? chil * d : d * chir;
-    const size_t np = (size_t)m * pad, nth = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = idx; e < np; e += nth) o[(e / pad) * ldk + k + e % pad] = cx<T>{T(0), T(0)};
-  }
-  if (idx >= (size_t)chil * chir) return;
+  const bool active = idx < (size_t)chil * chir;
   // rows_first: b fastest (contiguous columns s2'*chir + b); otherwise a fastest
-  int a, b;
-  if (rows_first) {
-    a = (int)(idx / chir);
-    b = (int)(idx % chir);
-  } else {
-    b = (int)(idx / chil);
-    a = (int)(idx % chil);
+  int a = 0, b = 0;
+  if (active) {
+    if (rows_first) {
+      a = (int)(idx / chir);
+      b = (int)(idx % chir);
+    } else {
+      b = (int)(idx / chil);
+      a = (int)(idx % chil);
+    }
   }
   const int D2 = d * d;
-  const cx<T>* q = qall + (size_t)c * D2 * D2;
   cx<T> v[VMAX];
-  const z64* th = theta + (size_t)a * D2 * chir + b;
-#pragma unroll
-  for (int x = 0; x < VMAX; ++x) {
-    if (x >= D2) break;
-    const z64 tv = th[(size_t)x * chir];
-    v[x] = cx<T>{T(tv.re), T(tv.im)};
-  }
-  for (int y = 0; y < D2; ++y) {
-    const int s1p = y / d, s2p = y - s1p * d;
-    cx<T> acc = {T(0), T(0)};
+  if (active) {
+    const z64* th = theta + (size_t)a * D2 * chir + b;
 #pragma unroll
     for (int x = 0; x < VMAX; ++x) {
       if (x >= D2) break;
-      acc = cadd(acc, cmul(q[y * D2 + x], v[x]));
+      const z64 tv = th[(size_t)x * chir];
+      v[x] = cx<T>{T(tv.re), T(tv.im)};
     }
-    const size_t row = rows_first ? (size_t)a * d + s1p : (size_t)s2p * chir + b;
-    const size_t col = rows_first ? (size_t)s2p * chir + b : (size_t)a * d + s1p;
-    o[row * ldk + col] = acc;
+  }
+  for (int u = 0; u < cpt; ++u) {
+    const int ls = g0 + u;
+    const int slot = c0 + ls;
+    if (ls >= cnt || (nlimit && slot >= *nlimit)) break;  // uniform over the block
+    const int c = list ? list[slot] : slot;
+    cx<T>* o = out + (size_t)ls * stride;
+    if (ldk > k) {
+      const int pad = ldk - k;
+      const size_t np = (size_t)m * pad, nth = (size_t)gridDim.x * blockDim.x;
+      for (size_t e = idx; e < np; e += nth) o[(e / pad) * ldk + k + e % pad] = cx<T>{T(0), T(0)};
+    }
+    if (!active) continue;
+    const cx<T>* q = qall + (size_t)c * D2 * D2;
+    for (int y = 0; y < D2; ++y) {
+      const int s1p = y / d, s2p = y - s1p * d;
+      cx<T> acc = {T(0), T(0)};
+#pragma unroll
+      for (int x = 0; x < VMAX; ++x) {
+        if (x >= D2) break;
+        acc = cadd(acc, cmul(q[y * D2 + x], v[x]));
+      }
+      const size_t row = rows_first ? (size_t)a * d + s1p : (size_t)s2p * chir + b;
+      const size_t col = rows_first ? (size_t)s2p * chir + b : (size_t)a * d + s1p;
+      o[row * ldk + col] = acc;
+    }
   }
 }
 
@@ -480,67 +497,78 @@ __device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
 
 // M_c = reshape(Q_c Theta) (as k_gen_rotated<float>) written as planes [Re hi, Re lo, Im hi, Im lo],
 // each m x k row-major BF16 with leading dimension ldk >= k (columns k..ldk-1 written as zeros);
-// candidate slot ls at out + ls * stride (stride = 4 m ldk elements).
+// candidate slot ls at out + ls * stride (stride = 4 m ldk elements); cpt candidates per
+// thread, as in k_gen_rotated.
 template <int DD>
 __global__ __launch_bounds__(256) void k_gen_rotated_bf16(int d_rt, int chil, int chir, const z64* __restrict__ theta,
                                                           const c32* __restrict__ qall, const int* __restrict__ list,
                                                           int c0, int cnt, const int* __restrict__ nlimit,
-                                                          __bf16* __restrict__ out, size_t stride, int ldk) {
+                                                          __bf16* __restrict__ out, size_t stride, int ldk,
+                                                          int cpt) {
   const int d = DD > 0 ? DD : d_rt;
   constexpr int VMAX = DD > 0 ? DD * DD : kMaxD * kMaxD;
-  const int ls = blockIdx.y;
-  const int slot = c0 + ls;
-  if (ls >= cnt || (nlimit && slot >= *nlimit)) return;
-  const int c = list ? list[slot] : slot;
   const bool rows_first = chil * d <= d * chir;
   const int k = rows_first ? d * chir : chil * d;
   const int m = rows_first ? chil * d : d * chir;
+  const int g0 = blockIdx.y * cpt;  // first candidate of this block's group
+  if (g0 >= cnt || (nlimit && c0 + g0 >= *nlimit)) return;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  __bf16* o = out + (size_t)ls * stride;
-  const size_t plane = (size_t)m * ldk;
-  if (ldk > k) {  // zero pad columns k..ldk-1 of every row of the four planes
-    const int pad = ldk - k;
-    const size_t np = (size_t)m * pad, nth = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = idx; e < np; e += nth) {
-      const size_t at = (e / pad) * ldk + k + e % pad;
-      for (int pl = 0; pl < 4; ++pl) o[pl * plane + at] = (__bf16)0.f;
+  const bool active = idx < (size_t)chil * chir;
+  int a = 0, b = 0;
+  if (active) {
+    if (rows_first) {
+      a = (int)(idx / chir);
+      b = (int)(idx % chir);
+    } else {
+      b = (int)(idx / chil);
+      a = (int)(idx % chil);
     }
   }
-  if (idx >= (size_t)chil * chir) return;
-  int a, b;
-  if (rows_first) {
-    a = (int)(idx / chir);
-    b = (int)(idx % chir);
-  } else {
-    b = (int)(idx / chil);
-    a = (int)(idx % chil);
-  }
   const int D2 = d * d;
-  const c32* q = qall + (size_t)c * D2 * D2;
   c32 v[VMAX];
-  const z64* th = theta + (size_t)a * D2 * chir + b;
-#pragma unroll
-  for (int x = 0; x < VMAX; ++x) {
-    if (x >= D2) break;
-    const z64 tv = th[(size_t)x * chir];
-    v[x] = c32{(float)tv.re, (float)tv.im};
-  }
-  for (int y = 0; y < D2; ++y) {
-    const int s1p = y / d, s2p = y - s1p * d;
-    c32 acc = {0.f, 0.f};
+  if (active) {
+    const z64* th = theta + (size_t)a * D2 * chir + b;
 #pragma unroll
     for (int x = 0; x < VMAX; ++x) {
       if (x >= D2) break;
-      acc = cadd(acc, cmul(q[y * D2 + x], v[x]));
+      const z64 tv = th[(size_t)x * chir];
+      v[x] = c32{(float)tv.re, (float)tv.im};
     }
-    const size_t row = rows_first ? (size_t)a * d + s1p : (size_t)s2p * chir + b;
-    const size_t col = rows_first ? (size_t)s2p * chir + b : (size_t)a * d + s1p;
-    const size_t e = row * ldk + col;
-    const __bf16 rh = (__bf16)acc.re, ih = (__bf16)acc.im;
-    o[e] = rh;
-    o[plane + e] = (__bf16)(acc.re - (float)rh);
-    o[2 * plane + e] = ih;
-    o[3 * plane + e] = (__bf16)(acc.im - (float)ih);
+  }
+  const size_t plane = (size_t)m * ldk;
+  for (int u = 0; u < cpt; ++u) {
+    const int ls = g0 + u;
+    const int slot = c0 + ls;
+    if (ls >= cnt || (nlimit && slot >= *nlimit)) break;  // uniform over the block
+    const int c = list ? list[slot] : slot;
+    __bf16* o = out + (size_t)ls * stride;
+    if (ldk > k) {  // zero pad columns k..ldk-1 of every row of the four planes
+      const int pad = ldk - k;
+      const size_t np = (size_t)m * pad, nth = (size_t)gridDim.x * blockDim.x;
+      for (size_t e = idx; e < np; e += nth) {
+        const size_t at = (e / pad) * ldk + k + e % pad;
+        for (int pl = 0; pl < 4; ++pl) o[pl * plane + at] = (__bf16)0.f;
+      }
+    }
+    if (!active) continue;
+    const c32* q = qall + (size_t)c * D2 * D2;
+    for (int y = 0; y < D2; ++y) {
+      const int s1p = y / d, s2p = y - s1p * d;
+      c32 acc = {0.f, 0.f};
+#pragma unroll
+      for (int x = 0; x < VMAX; ++x) {
+        if (x >= D2) break;
+        acc = cadd(acc, cmul(q[y * D2 + x], v[x]));
+      }
+      const size_t row = rows_first ? (size_t)a * d + s1p : (size_t)s2p * chir + b;
+      const size_t col = rows_first ? (size_t)s2p * chir + b : (size_t)a * d + s1p;
+      const size_t e = row * ldk + col;
+      const __bf16 rh = (__bf16)acc.re, ih = (__bf16)acc.im;
+      o[e] = rh;
+      o[plane + e] = (__bf16)(acc.re - (float)rh);
+      o[2 * plane + e] = ih;
+      o[3 * plane + e] = (__bf16)(acc.im - (float)ih);
+    }
   }
 }
 
@@ -1076,17 +1104,19 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
     __bf16* nb = reinterpret_cast<__bf16*>(nbuf);
     for (int c0 = 0; c0 < count; c0 += chunk) {
       const int cnt = std::min(chunk, count - c0);
-      const dim3 gg(blocks_for((size_t)chil * chir, 256), cnt), gp((unsigned)ntp * ((cnt + 7) / 8) * 8);
+      const int cpt = (!nlimit && cnt >= kGenMinChunk) ? kGenCands : 1;
+      const dim3 gg(blocks_for((size_t)chil * chir, 256), (cnt + cpt - 1) / cpt),
+          gp((unsigned)ntp * ((cnt + 7) / 8) * 8);
       const int ev = (evs && evused && 2 * (*evused) + 1 < evcap) ? 2 * (*evused) : -1;
       if (d == 3)
         hipLaunchKernelGGL((k_gen_rotated_bf16<3>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride, ldk);
+                           nlimit, nb, stride, ldk, cpt);
       else if (d == 2)
         hipLaunchKernelGGL((k_gen_rotated_bf16<2>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride, ldk);
+                           nlimit, nb, stride, ldk, cpt);
       else
         hipLaunchKernelGGL((k_gen_rotated_bf16<0>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride, ldk);
+                           nlimit, nb, stride, ldk, cpt);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
       hipLaunchKernelGGL(k_gram_purity_bf16, gp, dim3(256), 0, s, m, ldk, nb, stride, c0, cnt, nlimit, ntp, partial);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
@@ -1107,22 +1137,24 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
   const size_t stride = (size_t)m * ldk;
   const int chunk = (int)std::min<size_t>((size_t)count, nbuf_bytes / (stride * elem));
   GC_CHECK(chunk >= 1, GCAMPS_ECAPACITY, "rotated-matrix buffer too small");
-  const dim3 ggen(blocks_for((size_t)chil * chir, 256), chunk);
+
   for (int c0 = 0; c0 < count; c0 += chunk) {
     const int cnt = std::min(chunk, count - c0);
-    const dim3 gg(ggen.x, cnt), gp((unsigned)ntp * ((cnt + 7) / 8) * 8);
+    const int cpt = (!nlimit && cnt >= kGenMinChunk) ? kGenCands : 1;
+    const dim3 gg(blocks_for((size_t)chil * chir, 256), (cnt + cpt - 1) / cpt),
+        gp((unsigned)ntp * ((cnt + 7) / 8) * 8);
     const int ev = (evs && evused && 2 * (*evused) + 1 < evcap) ? 2 * (*evused) : -1;
     if (prec == GCAMPS_SCORE_FP64) {
       z64* nb = reinterpret_cast<z64*>(nbuf);
       if (d == 3)
         hipLaunchKernelGGL((k_gen_rotated<double, 3>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
-                           nlimit, nb, stride, ldk);
+                           nlimit, nb, stride, ldk, cpt);
       else if (d == 2)
         hipLaunchKernelGGL((k_gen_rotated<double, 2>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
-                           nlimit, nb, stride, ldk);
+                           nlimit, nb, stride, ldk, cpt);
       else
         hipLaunchKernelGGL((k_gen_rotated<double, 0>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
-                           nlimit, nb, stride, ldk);
+                           nlimit, nb, stride, ldk, cpt);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
       hipLaunchKernelGGL((k_gram_purity<double, 2, 4>), gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
                          partial);
@@ -1131,13 +1163,13 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
       c32* nb = reinterpret_cast<c32*>(nbuf);
       if (d == 3)
         hipLaunchKernelGGL((k_gen_rotated<float, 3>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride, ldk);
+                           nlimit, nb, stride, ldk, cpt);
       else if (d == 2)
         hipLaunchKernelGGL((k_gen_rotated<float, 2>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride, ldk);
+                           nlimit, nb, stride, ldk, cpt);
       else
         hipLaunchKernelGGL((k_gen_rotated<float, 0>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
-                           nlimit, nb, stride, ldk);
+                           nlimit, nb, stride, ldk, cpt);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
       hipLaunchKernelGGL(k_gram_purity_dl, gp, dim3(512), 0, s, m, ldk, nb, stride, c0, cnt, nlimit, ntp, partial);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
