@@ -2,14 +2,16 @@
 states whose two-site shapes reach every branch of the tiled Gram-purity kernels (§3: each
 candidate's S2 is minus the log of the purity of the reduced state of Q_c Theta).
 
-With m the smaller and k the larger side of the two-site matrix, the FP32 path takes
-  - the fused small kernel for m <= 96,
-  - the direct-to-LDS tiled kernel for k a multiple of 16: here with an odd number of 16-column
-    chunks and m < 128 (m = k = 112: one tile, rows 112..127 clamped), with an odd chunk count
-    and a partial second tile (m = k = 240), and with even chunk counts (m = 128 or 256,
-    k = 256),
-  - the register-staged tiled kernel otherwise (m = 243, k = 729, both orientations).
-The BF16 path runs its own tiled kernel on the same shapes.
+With m the smaller and k the larger side of the two-site matrix, the FP32 path takes the fused
+small kernel for m <= 96 and the direct-to-LDS tiled kernel above that, on rows padded with
+zero columns to a multiple of 16.  The shapes reach it
+  - with an odd number of 16-column chunks and m < 128 (m = k = 112: one tile, rows 112..127
+    clamped),
+  - with an odd chunk count and a partial second tile (m = k = 240),
+  - with even chunk counts (m = 128, k = 256, both orientations),
+  - with padded rows (m = 243, k = 729 -> 736, both orientations).
+The BF16 path runs its own direct-to-LDS kernel (planes padded to a multiple of 32) on the same
+shapes.
 
 Bar: |S2 - S2_oracle| <= 5e-5 for every candidate, the bound under which the FP64 re-score
 of the near-tie window (near_tie = 1e-4) makes the choice; rounding puts the FP32 error near
@@ -62,7 +64,7 @@ def branch(d, cl, cr):
     if m <= 96:
         return "small"
     if k % 16:
-        return "staged"
+        return "padded"
     odd = (k // 16) % 2 == 1
     return "dl-odd-m<128" if odd and m < 128 else "dl-odd-partial" if odd and m % 128 else "dl"
 
@@ -71,7 +73,7 @@ CASES = [  # d, n, chi_max, layers, branches that must occur
     (2, 14, 56, 28, {"dl-odd-m<128"}),
     (3, 10, 80, 20, {"dl-odd-partial"}),
     (2, 15, 128, 30, {"dl"}),
-    (3, 11, 243, 14, {"staged"}),
+    (3, 11, 243, 14, {"padded"}),
 ]
 
 
