@@ -24,7 +24,10 @@ A second workload measures batching of independent circuits (qutrits, circuit i 
 n_i ~ U{8..48} sites, T_i ~ U{4..60} T gates at uniform positions, 2 n_i layers,
 chi_max = 128, cutoff 1e-10, 512 shared candidates, FP32-scored) on concurrent lanes:
 
-    python bench.py --workload batch [--batch-count C] [--lanes L]
+    python bench.py --workload batch [--batch-count C] [--lanes L] [--batch-chunk K]
+
+All 256 circuits take several minutes; --batch-chunk K submits them K at a time and prints
+progress after each chunk (at the cost of lanes idling at each chunk's end).
 
 A third measures the reverse-mode gradient of Re sum_j <Z_j> with respect to 64 phase
 angles (qutrits, n = 24, 48 layers, 32 parametrised gates, chi_max = 256, cutoff 1e-10,
