@@ -121,6 +121,7 @@ class Gcamps:
         self.tab = Tableau(d, n)
         self.mps = MPS.product_zero(d, n)
         self.f_est = 1.0
+        self.eps_log: List[float] = []      # discarded weight of every truncation, in order
         self.choice_log: List[ChoiceEntry] = []
         self.gate_count = 0
         self.flags = 0                      # number of degenerate cuts (parity unpinned)
@@ -158,6 +159,7 @@ class Gcamps:
             self.rank_log.extend(self.mps.last_ks)
             for e in epss:
                 self.f_est *= (1.0 - e)
+                self.eps_log.append(float(e))
             self.flags += sum(flags)
         self.gate_count += 1
         if self.cfg.auto_disentangle and self.candidates:
@@ -191,6 +193,7 @@ class Gcamps:
             self.rank_log.extend(self.mps.last_ks)
             for e in epss:
                 self.f_est *= (1.0 - e)
+                self.eps_log.append(float(e))
             self.flags += sum(flags)
         self.gate_count += 1
         if self.cfg.auto_disentangle and self.candidates:
@@ -262,6 +265,7 @@ class Gcamps:
                                                     move_right=left_to_right, force_k=force)
                 self.rank_log.append(kept)
                 self.f_est *= (1.0 - eps)
+                self.eps_log.append(float(eps))
                 self.flags += int(flagged)
             changed_total += changed
             if changed == 0:

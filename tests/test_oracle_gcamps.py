@@ -190,3 +190,29 @@ def test_coset_count_matches_paper(d):
     local = _group_order(gens[:4], d)
     assert full == d ** 4 * (d * d - 1) * (d ** 4 - 1)
     assert full // local == want[d]
+
+
+@pytest.mark.parametrize("d,n,layers,t,chi_max,cutoff,seed", [
+    (3, 6, 12, 8, 27, 1e-3, 73),     # truncation by the cutoff
+    (2, 10, 20, 12, 8, 0.0, 74),     # truncation by chi_max
+])
+def test_truncated_state_within_the_angle_bound(d, n, layers, t, chi_max, cutoff, seed):
+    """Truncated regime against the dense simulation of the same circuit.  The Fubini-Study
+    angle arccos|<a|b>| is a metric on normalised states; unitary gates and the Clifford
+    frame updates preserve it, and a truncation that keeps weight 1 - eps of a normalised
+    state and renormalises moves it by exactly arcsin(sqrt(eps)).  So the final state obeys
+    |<psi_exact|psi>|^2 >= cos^2(sum_k arcsin sqrt(eps_k)) over all truncations k.  A
+    discarded weight reported too small, a missing renormalisation or a wrong frame C breaks
+    this; the cases are chosen so that the bound is far from trivial."""
+    c = brickwork_circuit(d, n, layers, t, seed=seed)
+    g = run_circuit(c, candidate_words(d, 16, seed), Config(chi_max=chi_max, cutoff=cutoff))
+    psi, ref = g.statevector(), simulate(c)
+    assert abs(np.linalg.norm(psi) - 1.0) < 1e-12
+    eps = np.array(g.eps_log)
+    assert np.all(eps >= 0.0) and np.count_nonzero(eps) >= 10    # truncation did happen
+    assert abs(np.prod(1.0 - eps) - g.f_est) <= 1e-12 * g.f_est  # F_est is the product (§2.4)
+    angle = float(np.sum(np.arcsin(np.sqrt(eps))))
+    assert angle < 0.6                                           # bound >= cos^2(0.6) = 0.68
+    f_true = abs(np.vdot(ref, psi)) ** 2
+    assert f_true < 1.0 - 1e-4                                   # truncation mattered
+    assert f_true >= np.cos(angle) ** 2 - 1e-12
