@@ -216,3 +216,37 @@ def test_truncated_state_within_the_angle_bound(d, n, layers, t, chi_max, cutoff
     f_true = abs(np.vdot(ref, psi)) ** 2
     assert f_true < 1.0 - 1e-4                                   # truncation mattered
     assert f_true >= np.cos(angle) ** 2 - 1e-12
+
+
+@pytest.mark.parametrize("d,n,layers,k,chi_max,cutoff,seed", [
+    (3, 6, 12, 1, 27, 1e-3, 81),     # Haar-random one-qutrit gates
+    (2, 8, 16, 2, 16, 1e-4, 83),     # Haar-random two-qubit gates
+])
+def test_general_gate_truncation_within_the_angle_bound(d, n, layers, k, chi_max, cutoff, seed):
+    """The same angle bound for general gates (their J-term MPOs are compressed by truncating
+    sweeps), against a dense product of the circuit's gates in the order the oracle applies
+    them: bricks, phase gates, then general gates, layer by layer."""
+    from oracle.statevector import apply_one_site, apply_two_site
+    from paper_2511_06672_amd.workload import general_circuit
+    c = general_circuit(d, n, layers, k, seed)
+    g = run_circuit(c, candidate_words(d, 16, seed), Config(chi_max=chi_max, cutoff=cutoff))
+    ref = np.zeros(d ** n, dtype=np.complex128)
+    ref[0] = 1.0
+    for layer in c.layers:
+        for b in layer.bricks:
+            ref = apply_two_site(ref, d, n, b.site, word_matrix(d, b.word.gens, b.word.weyl))
+        for ph in layer.phases:
+            ref = apply_one_site(ref, d, n, ph.site, np.diag(np.exp(1j * np.asarray(ph.phi))))
+        for gg in layer.gates:
+            u = np.array(gg.u).reshape(d ** gg.k, d ** gg.k)
+            ref = (apply_one_site if gg.k == 1 else apply_two_site)(ref, d, n, gg.site, u)
+    assert c.n_general_gates > 0
+    psi = g.statevector()
+    assert abs(np.linalg.norm(psi) - 1.0) < 1e-12
+    eps = np.array(g.eps_log)
+    assert np.count_nonzero(eps) >= 10
+    angle = float(np.sum(np.arcsin(np.sqrt(eps))))
+    assert angle < 0.6
+    f_true = abs(np.vdot(ref, psi)) ** 2
+    assert f_true < 1.0 - 1e-4
+    assert f_true >= np.cos(angle) ** 2 - 1e-12
