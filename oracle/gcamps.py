@@ -129,6 +129,14 @@ class Gcamps:
         self.candidates = list(candidates)
         self._cand_mats = [word_matrix(d, w.gens, w.weyl) for w in self.candidates]
         self.last_support: Tuple[int, int] = (-1, -1)
+        # Bookkeeping for the reverse-mode derivative (oracle/adjoint.py), no arithmetic:
+        # every step that changes the state of the MPS, in execution order --
+        #   ("mpo", l, r, ops, phi, phase)  sum_b c_b(phi) phase[b] (x)_{i=l..r} ops[b][i-l]
+        #   ("cut", c, k)                   truncating split across the cut after site c-1,
+        #                                   k values kept, renormalised
+        #   ("q", i, Q)                     disentangler unitary on sites (i, i+1)
+        # Exact centre moves leave the state unchanged and are not listed.
+        self.steps: List[tuple] = []
 
     # ------------------------------------------------------------------ top loop
     def apply_clifford(self, site: int, gens: Sequence[int], weyl: Sequence[int]):
@@ -148,6 +156,8 @@ class Gcamps:
         coeff = np.array([c[b] * tau(d) ** powers[b].p for b in range(d)])
         ops = [[site_matrix(d, int(powers[b].x[i]), int(powers[b].z[i])) for i in range(l, r + 1)]
                for b in range(d)]
+        self.steps.append(("mpo", l, r, ops, tuple(float(v) for v in phi),
+                           np.array([tau(d) ** powers[b].p for b in range(d)])))
         self.mps.move_centre(l)
         self.mps.apply_block_mpo(l, r, ops, coeff)
         if r > l:
@@ -157,6 +167,7 @@ class Gcamps:
             epss, flags = self.mps.truncate_sweep_left(l, r, self.cfg.cutoff, self.cfg.chi_max,
                                                        force_ks=force)
             self.rank_log.extend(self.mps.last_ks)
+            self.steps.extend(("cut", i, k) for i, k in zip(range(r, l, -1), self.mps.last_ks))
             for e in epss:
                 self.f_est *= (1.0 - e)
                 self.eps_log.append(float(e))
@@ -259,11 +270,13 @@ class Gcamps:
                                    th.reshape(cl, d * d, cr)).reshape(cl, d, d, cr)
                     self.tab.right_multiply_dagger(i, w.gens, w.weyl)
                     self.record.append(("Q", i, tuple(w.gens), tuple(w.weyl)))
+                    self.steps.append(("q", i, self._cand_mats[c]))
                     changed += 1
                 force = self._frozen_ranks.pop(0) if self._frozen_ranks is not None else None
                 eps, flagged, kept = self.mps.split(i, th, self.cfg.cutoff, self.cfg.chi_max,
                                                     move_right=left_to_right, force_k=force)
                 self.rank_log.append(kept)
+                self.steps.append(("cut", i + 1, kept))
                 self.f_est *= (1.0 - eps)
                 self.eps_log.append(float(eps))
                 self.flags += int(flagged)
