@@ -39,6 +39,24 @@ def candidates(wl):
     return wl.candidates
 
 
+def finish(rec, g, out_path):
+    """Record the final state at the end of the covered prefix: <Z_j> for every site and the
+    tableau.  Written once, after the last covered gate."""
+    zs = []
+    for j in range(g.n):
+        z = np.zeros(g.n, np.int64)
+        z[j] = 1
+        v = g.expectation(np.zeros(g.n, np.int64), z, 0)
+        zs.append([v.real, v.imag])
+    rec["final_z_expectations"] = zs
+    rec["final_tableau"] = g.tab.export().tolist()
+    rec["final_after_gates"] = rec.get("gates_done", 0)
+    with open(out_path + ".tmp", "w") as f:
+        json.dump(rec, f)
+    os.replace(out_path + ".tmp", out_path)
+    print(f"final <Z_j> written after {rec['final_after_gates']} gates", flush=True)
+
+
 def main():
     d = int(sys.argv[1])
     max_gates = int(sys.argv[2]) if len(sys.argv) > 2 else 10 ** 6
@@ -60,7 +78,7 @@ def main():
             g.apply_clifford(b.site, b.word.gens, b.word.weyl)
         for gg in layer.gates:
             if gi >= max_gates or time.time() - t_start > budget:
-                return
+                return finish(rec, g, out_path)
             t0 = time.time()
             D = c.d ** gg.k
             g.apply_gate(gg.site, np.array(gg.u, dtype=complex).reshape(D, D))
@@ -79,6 +97,7 @@ def main():
             os.replace(out_path + ".tmp", out_path)
             print(f"gate {gi} maxchi {max(g.mps.bond_dims())} f {g.f_est:.15f} {dt:.1f}s", flush=True)
             gi += 1
+    finish(rec, g, out_path)
 
 
 if __name__ == "__main__":

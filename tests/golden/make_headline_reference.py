@@ -71,9 +71,11 @@ def main():
         zs.append([v.real, v.imag])
     rec["final_z_expectations"] = zs
     rec["final_tableau"] = g.tab.export().tolist()
+    rec["final_after_gates"] = rec["gates_done"]
     with open(out_path + ".tmp", "w") as f:
         json.dump(rec, f)
     os.replace(out_path + ".tmp", out_path)
+    print("final <Z_j> written", flush=True)
 
 
 if __name__ == "__main__":

@@ -22,6 +22,22 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 F_TOL = 1e-9
+Z_TOL = 1e-8     # final <Z_j>: every scoring mode commits with the same FP64 factorisations
+
+
+def check_final_state(st, ref, n, tol):
+    """<Z_j> for every site and the whole tableau after the reference's last gate (§3
+    observables: C^dagger Z_j C evaluated on the MPS by transfer matrices)."""
+    if "final_z_expectations" not in ref:  # written by the reference scripts after the last gate
+        print("[gpu-case] reference holds no final state", flush=True)
+        return
+    want = np.array(ref["final_z_expectations"])
+    got = np.array([[v.real, v.imag] for v in
+                    (st.expectation([0] * n, [1 if k == j else 0 for k in range(n)]) for j in range(n))])
+    err = float(np.max(np.abs(got - want)))
+    print(f"[gpu-case] final <Z_j>: largest difference {err:.2e}", flush=True)
+    assert err <= tol, f"final <Z_j> differ by {err:.3e}"
+    assert np.array_equal(st.tableau(), np.array(ref["final_tableau"])), "final tableau differs"
 
 
 def digest(tab):
@@ -66,3 +82,4 @@ def test_general_workload_against_oracle_reference(name, prec):
             assert abs(st.fidelity() - r["f_est"]) <= F_TOL * r["f_est"], f"fidelity differs at gate {gi}"
             gi += 1
     assert gi == ngates
+    check_final_state(st, ref, c.n, Z_TOL)
