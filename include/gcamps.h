@@ -87,7 +87,10 @@ typedef struct {
   int32_t chi_max;          /* maximal bond dimension kept by truncation */
   double cutoff;            /* discarded relative weight allowed per bond (R-TRUNC) */
   int32_t score_prec;       /* GCAMPS_SCORE_* */
-  double near_tie;          /* low-precision re-score window in S2 units (>= 1e-6) */
+  double near_tie;          /* low-precision re-score window in S2 units: >= 1e-4 with FP32 or
+                               split-BF16 scoring (at least twice their measured S2 error, so the
+                               FP64 choice is always inside the window), >= 1e-6 with replica
+                               scoring; unused with FP64 scoring */
   double tie_tol;           /* FP64 tie tolerance of the argmin (default 1e-10) */
   int32_t max_sweeps;       /* disentangling sweeps per non-Clifford gate (default 2) */
   int32_t auto_disentangle; /* 1: gcamps_apply_phase_rotation disentangles afterwards */
@@ -144,8 +147,16 @@ int32_t gcamps_apply_clifford_layer(gcamps_ctx* ctx, const int32_t* sites,
 int32_t gcamps_apply_phase_rotation(gcamps_ctx* ctx, int32_t site, const double* phi);
 
 /* Compile candidate disentanglers (§3: two-qudit Cliffords Q whose application
- * to the MPS is compensated by C <- C Q^dagger).  words[0] must be the identity
- * (len 0, zero Weyl shift).  Host object; count >= 1. Errors: EINVAL. */
+ * to the MPS is compensated by C <- C Q^dagger) into a host object holding, per word, its
+ * d^4-entry conjugation table and its d^2 x d^2 unitary.  words[0] must be the identity
+ * (len 0, zero Weyl shift); count >= 1; `words` is borrowed for the call.  The set is
+ * released by gcamps_candset_destroy (NULL is a no-op).
+ * Errors: EINVAL (null pointer, count < 1, d not a prime in 2..7, first word not the
+ * identity, generator code or Weyl exponent out of range). */
+int32_t gcamps_candset_create(int32_t d, const gcamps_word* words, int32_t count,
+                              gcamps_candset** out);
+int32_t gcamps_candset_destroy(gcamps_candset* set);
+
 /* Exhaustive two-qudit Clifford sets as generator words (§3, §3.1), without Weyl shifts, the
  * identity first.  Up to Weyl shifts a pair Clifford is its 4x4 symplectic matrix over Z_d.
  *   GCAMPS_WORDS_DISENTANGLERS: one word per class of Cliffords that differ only by
@@ -175,25 +186,11 @@ int32_t gcamps_clifford_words(int32_t d, int32_t kind, int32_t* lens, int32_t le
  * ECAPACITY (J > max(d, max_gate_terms)), ENUMERIC, EDEVICE. */
 int32_t gcamps_apply_gate(gcamps_ctx* ctx, int32_t site, int32_t nsites, const double* u);
 
-int32_t gcamps_candset_create(int32_t d, const gcamps_word* words, int32_t count,
-                              gcamps_candset** out);
-int32_t gcamps_candset_destroy(gcamps_candset* set);
 
 /* Attach a candidate set used by auto-disentangling (uploads it to the device).
  * Errors: EINVAL (d mismatch), ECAPACITY (count > max_candidates), EDEVICE. */
 int32_t gcamps_set_candset(gcamps_ctx* ctx, const gcamps_candset* set);
 
-/* Disentangling sweeps (§3): sweep s runs over bonds 0..n-2 (s even) or n-2..0
- * (s odd).  At each bond the two-site tensor Theta is rotated by every
- * candidate Q_c and scored by the Renyi-2 entropy of its middle cut,
- * S2_c = -ln(sum |rho_c|^2 / (tr rho_c)^2), rho_c = M_c M_c^dagger; the chosen
- * c* is the lowest index with S2_c <= min S2 + tie_tol (in FP64; in FP32 mode
- * every candidate within near_tie of the FP32 minimum is re-scored in FP64
- * first).  If c* != 0: Theta <- Q Theta, C <- C Q^dagger.  Theta is then split
- * with the truncation rule.  Sweeping stops after a sweep with c* = 0
- * everywhere or after max_sweeps.  set may be NULL to use the attached set.
- * out_sweeps / out_changed_bonds may be NULL.
- * Errors: EINVAL, ECAPACITY, ENUMERIC, EDEVICE. */
 /* S2 of every candidate of the attached set at bond (bond, bond + 1) of the current state, the
  * disentangler's full-set score (§3; the Rényi-2 entropy of the rotated two-site tensor is how
  * this library reads the paper's entanglement measure) in the ctx's scoring mode (FP32/BF16: the low-precision first
@@ -208,16 +205,34 @@ int32_t gcamps_score_bond(gcamps_ctx* ctx, int32_t bond, double* out, int64_t ca
  * to a caller's matrix so that it can be checked on its own.  m_host: p x q complex128,
  * row-major, interleaved (re, im), borrowed.  Requires min(p, q) and p * q within the ctx's
  * capacity (min(p, q) <= chi_max * max(d, max_gate_terms), p * q <= that times d times itself).
- * Outputs (host): sig_out[min(p, q)] all singular values in descending order; *kept the rank
+ * flags: 0, or GCAMPS_FACTORIZE_REDUCE for the path of the splits after a disentangler: with a
+ * positive cutoff and min(p, q) > 32, a pivoted Cholesky factorisation of the Gram first finds a
+ * basis of r columns holding all but at most min(1e-14, cutoff / (2 min(p, q))) of the weight
+ * and the eigensolver runs on r x r; the remainder counts as discarded.  Without a useful
+ * reduction (r > 3/4 min(p, q)) the full path runs.
+ * Outputs (host): sig_out[min(p, q)] the singular values in descending order (with
+ * GCAMPS_FACTORIZE_REDUCE those of the reduced basis, zeros after them); *kept the rank
  * kept; *eps the discarded weight sum_{i >= kept} sigma_i^2 / sum_i sigma_i^2; if non-NULL,
  * l_out[p * kept] the left factor U_k (orthonormal columns, row-major complex128) and
  * r_out[kept * q] the right factor diag(s_k) V_k^dagger with s_k the kept singular values
  * scaled to unit norm (row-major complex128), so that L R = M_k / |M_k|.  The state of the ctx
- * is not changed.  Errors: EINVAL (null pointer, p or q < 1), ECAPACITY, EUNSUPPORTED (ctx of a
- * gradient recording), ENUMERIC, EDEVICE. */
-int32_t gcamps_factorize(gcamps_ctx* ctx, const double* m_host, int32_t p, int32_t q, double* sig_out,
-                         int32_t* kept, double* eps, double* l_out, double* r_out);
+ * is not changed.  Errors: EINVAL (null pointer, p or q < 1, unknown flag), ECAPACITY,
+ * EUNSUPPORTED (ctx of a gradient recording), ENUMERIC, EDEVICE. */
+enum { GCAMPS_FACTORIZE_REDUCE = 1 };
+int32_t gcamps_factorize(gcamps_ctx* ctx, const double* m_host, int32_t p, int32_t q, int32_t flags,
+                         double* sig_out, int32_t* kept, double* eps, double* l_out, double* r_out);
 
+/* Disentangling sweeps (§3): sweep s runs over bonds 0..n-2 (s even) or n-2..0
+ * (s odd).  At each bond the two-site tensor Theta is rotated by every
+ * candidate Q_c and scored by the Renyi-2 entropy of its middle cut,
+ * S2_c = -ln(sum |rho_c|^2 / (tr rho_c)^2), rho_c = M_c M_c^dagger; the chosen
+ * c* is the lowest index with S2_c <= min S2 + tie_tol (in FP64; in FP32 mode
+ * every candidate within near_tie of the FP32 minimum is re-scored in FP64
+ * first).  If c* != 0: Theta <- Q Theta, C <- C Q^dagger.  Theta is then split
+ * with the truncation rule.  Sweeping stops after a sweep with c* = 0
+ * everywhere or after max_sweeps.  set may be NULL to use the attached set.
+ * out_sweeps / out_changed_bonds may be NULL.
+ * Errors: EINVAL, ECAPACITY, ENUMERIC, EDEVICE. */
 int32_t gcamps_disentangle(gcamps_ctx* ctx, const gcamps_candset* set, int32_t* out_sweeps,
                            int32_t* out_changed_bonds);
 
@@ -229,14 +244,23 @@ int32_t gcamps_expectation(gcamps_ctx* ctx, const int8_t* x, const int8_t* z, in
 
 /* Dense psi = C|MPS> into dev_out (d^n complex128, interleaved re/im, device
  * memory), defined up to one global phase (the tableau fixes C only up to a
- * phase).  dev_scratch: device memory of at least 2 * 16 * d^n bytes.  Only for
- * d^n <= 2^20.  Errors: EINVAL, EUNSUPPORTED (d^n too large), EDEVICE. */
+ * phase).  For validation at small sizes: d^n <= 2^16.  dev_scratch: device
+ * memory of at least 3 * 16 * d^n bytes, borrowed for the call; the per-index
+ * Clifford table goes into the ctx's workspace (gcamps_workspace_bytes counts
+ * it whenever d^n <= 2^16).  Nothing is allocated.  Synchronises the stream.
+ * Errors: EINVAL (null pointer), EUNSUPPORTED (d^n > 2^16), EWORKSPACE
+ * (scratch_bytes too small), ENUMERIC, EDEVICE. */
 int32_t gcamps_statevector(gcamps_ctx* ctx, void* dev_out, void* dev_scratch,
                            size_t scratch_bytes);
 
-/* One amplitude <digits|psi> (same global-phase convention as
- * gcamps_statevector); digits: n host values in [0, d).  d^n <= 2^20.
- * Errors: EINVAL, EUNSUPPORTED, EDEVICE. */
+/* One amplitude <digits|psi> of psi = C|MPS> (§3), same global-phase convention
+ * as gcamps_statevector.  For validation at small sizes (d^n <= 2^16): the dense
+ * state is formed in the ctx's own workspace (4 * 16 * d^n bytes plus the
+ * per-index table, counted by gcamps_workspace_bytes), so nothing is allocated,
+ * and the one requested entry is returned.  digits: n host values in [0, d),
+ * site 0 most significant.  Synchronises the stream.
+ * Errors: EINVAL (null pointer, digit out of range), EUNSUPPORTED (d^n > 2^16),
+ * ENUMERIC, EDEVICE. */
 int32_t gcamps_amplitude(gcamps_ctx* ctx, const int8_t* digits, double out[2]);
 
 /* Tableau as an int32 [2n][2n+1] matrix: rows 0..n-1 = S_k = C Z_k C^dagger,
@@ -271,7 +295,9 @@ int32_t gcamps_get_stats(gcamps_ctx* ctx, double out[16]);
  * SVD with p >= q (the R-SVD operation count, complex); [2] their device time in ms (Gram
  * product to truncation rule, second pass included; the emit of the factors excluded);
  * [3] MPO site launches; [4] their algorithmic bytes (each site tensor read once, its product
- * written once, complex128); [5] their device time in ms; [6], [7] 0.  out: host array of 8
+ * written once, complex128); [5] their device time in ms; [6] splits of rotated two-site
+ * tensors whose eigen-decomposition ran on a rank-reduced basis (pivoted Cholesky of the Gram),
+ * [7] their summed basis size over their summed matrix side (0 when none).  out: host array of 8
  * doubles.  Synchronises the ctx's stream.  Errors: EINVAL, EDEVICE. */
 int32_t gcamps_get_kernel_stats(gcamps_ctx* ctx, double out[8]);
 

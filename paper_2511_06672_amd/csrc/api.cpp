@@ -55,7 +55,12 @@ void validate_config(const gcamps_config* c) {
   GC_CHECK(c->score_prec != GCAMPS_SCORE_REPLICA || c->d <= 3, GCAMPS_EUNSUPPORTED,
            "replica scoring is implemented for d = 2 and 3");
   GC_CHECK(c->tie_tol >= 0.0, GCAMPS_EINVAL, "tie_tol must be >= 0");
+  // The FP64 re-score decides only among candidates inside the window, so the window must be
+  // wider than twice the low-precision scoring error (measured up to ~2e-5 in S2 for FP32 and
+  // split BF16); replica scoring is FP64 arithmetic and needs only the FP64 floor.
   GC_CHECK(c->score_prec == GCAMPS_SCORE_FP64 || c->near_tie >= 1e-6, GCAMPS_EINVAL, "near_tie must be >= 1e-6");
+  GC_CHECK((c->score_prec != GCAMPS_SCORE_FP32 && c->score_prec != GCAMPS_SCORE_BF16) || c->near_tie >= kNearTieLowp,
+           GCAMPS_EINVAL, "near_tie must be >= 1e-4 with FP32 or split-BF16 scoring");
   GC_CHECK(c->max_sweeps >= 0, GCAMPS_EINVAL, "max_sweeps must be >= 0");
   GC_CHECK(c->max_candidates >= 1 && c->max_candidates <= 65536, GCAMPS_EINVAL, "max_candidates out of range");
 }
@@ -151,6 +156,13 @@ Layout make_layout(const gcamps_config& c) {
   L.off_status = take(sizeof(DevStatus));
   L.off_luts = take((size_t)c.n * D4 * sizeof(uint32_t));
   L.off_sites = take((size_t)c.n * sizeof(int));
+  // dense state (validation; d^n <= kDenseMax): amplitude output and scratch (4 d^n complex128)
+  // plus the per-index Clifford table (two int32 and n int8 per index)
+  L.dense_dim = 1;
+  for (int i = 0; i < c.n && L.dense_dim <= kDenseMax; ++i) L.dense_dim *= d;
+  if (L.dense_dim > kDenseMax) L.dense_dim = 0;
+  L.off_dense = take(L.dense_dim * (4 * sizeof(z64) + 2 * sizeof(int) + (size_t)c.n));
+  L.off_pcst = take(sizeof(PcState));
   L.total = o;
   return L;
 }
@@ -236,6 +248,7 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
     c->st = reinterpret_cast<DevStatus*>(w + lay.off_status);
     c->dluts = reinterpret_cast<uint32_t*>(w + lay.off_luts);
     c->dsites = reinterpret_cast<int*>(w + lay.off_sites);
+    c->pcst = reinterpret_cast<PcState*>(w + lay.off_pcst);
     c->pinned_bytes = std::max<size_t>(1 << 20, (size_t)n * 2401 * 4 + 4096);
     GC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->pinned), c->pinned_bytes, hipHostMallocDefault));
     GC_HIP(hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming));
@@ -420,10 +433,11 @@ int32_t gcamps_score_bond(gcamps_ctx* ctx, int32_t bond, double* out, int64_t ca
   });
 }
 
-int32_t gcamps_factorize(gcamps_ctx* ctx, const double* m_host, int32_t p, int32_t q, double* sig_out,
-                         int32_t* kept, double* eps, double* l_out, double* r_out) {
+int32_t gcamps_factorize(gcamps_ctx* ctx, const double* m_host, int32_t p, int32_t q, int32_t flags,
+                         double* sig_out, int32_t* kept, double* eps, double* l_out, double* r_out) {
   return guarded(ctx, [&] {
     GC_CHECK(ctx && m_host && sig_out && kept && eps, GCAMPS_EINVAL, "null argument");
+    GC_CHECK((flags & ~GCAMPS_FACTORIZE_REDUCE) == 0, GCAMPS_EINVAL, "unknown factorize flag");
     GC_CHECK(p >= 1 && q >= 1, GCAMPS_EINVAL, "matrix must be at least 1 x 1");
     GC_CHECK(ctx->tape == nullptr && ctx->rank_rec == nullptr && ctx->rank_frz == nullptr, GCAMPS_EUNSUPPORTED,
              "factorize is not available on a gradient recording");
@@ -431,8 +445,11 @@ int32_t gcamps_factorize(gcamps_ctx* ctx, const double* m_host, int32_t p, int32
     GC_CHECK(m <= ctx->lay.mcap && pq <= ctx->lay.slot_elems, GCAMPS_ECAPACITY,
              "matrix exceeds the ctx's factorisation capacity");
     GC_HIP(hipMemcpyAsync(ctx->theta, m_host, pq * sizeof(z64), hipMemcpyHostToDevice, ctx->stream));
-    const DevStatus h = ctx->factorize(ctx->theta, p, q, 0, 1, ctx->Lbuf, ctx->Rbuf);
-    GC_HIP(hipMemcpyAsync(sig_out, ctx->sig, m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    const DevStatus h =
+        ctx->factorize(ctx->theta, p, q, 0, 1, ctx->Lbuf, ctx->Rbuf, (flags & GCAMPS_FACTORIZE_REDUCE) != 0);
+    const size_t nb = (size_t)ctx->last_basis;  // values the factorisation resolved (m, or r when reduced)
+    GC_HIP(hipMemcpyAsync(sig_out, ctx->sig, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    for (size_t i = nb; i < m; ++i) sig_out[i] = 0.0;
     if (l_out)
       GC_HIP(hipMemcpyAsync(l_out, ctx->Lbuf, (size_t)p * h.kept * sizeof(z64), hipMemcpyDeviceToHost, ctx->stream));
     if (r_out)
@@ -499,14 +516,13 @@ int32_t gcamps_expectation(gcamps_ctx* ctx, const int8_t* x, const int8_t* z, in
 }
 
 static long long dense_dim(gcamps_ctx* ctx) {
-  long long D = 1;
-  for (int i = 0; i < ctx->n; ++i) {
-    D *= ctx->d;
-    GC_CHECK(D <= (1LL << 16), GCAMPS_EUNSUPPORTED, "dense state limited to d^n <= 2^16");
-  }
-  return D;
+  GC_CHECK(ctx->lay.dense_dim > 0, GCAMPS_EUNSUPPORTED, "dense state limited to d^n <= 2^16");
+  return (long long)ctx->lay.dense_dim;
 }
 
+// Dense psi = C|MPS> into out (D complex128); scratch holds 3 D complex128.  The per-index
+// Clifford table lives in the ctx's dense region after its 4 D complex128, so nothing is
+// allocated here.
 static void statevector_impl(gcamps_ctx* ctx, z64* out, z64* scratch) {
   const int n = ctx->n, d = ctx->d;
   const long long D = dense_dim(ctx);
@@ -603,13 +619,7 @@ static void statevector_impl(gcamps_ctx* ctx, z64* out, z64* scratch) {
     px[x] = p;
     for (int i = 0; i < n; ++i) bd[(size_t)x * n + i] = (int8_t)bz[i];
   }
-  // validation-only table: allocated per call
-  char* tbl = nullptr;
-  GC_HIP(hipMalloc(reinterpret_cast<void**>(&tbl), (size_t)D * (2 * sizeof(int) + n)));
-  struct FreeTbl {
-    char* p;
-    ~FreeTbl() { (void)hipFree(p); }
-  } free_tbl{tbl};
+  char* tbl = ctx->ws + ctx->lay.off_dense + (size_t)4 * D * sizeof(z64);
   int* d_aidx = reinterpret_cast<int*>(tbl);
   int* d_px = d_aidx + D;
   int8_t* d_bd = reinterpret_cast<int8_t*>(d_px + D);
@@ -638,12 +648,8 @@ int32_t gcamps_amplitude(gcamps_ctx* ctx, const int8_t* digits, double out[2]) {
       GC_CHECK(digits[i] >= 0 && digits[i] < ctx->d, GCAMPS_EINVAL, "digit out of range");
       y = y * ctx->d + digits[i];
     }
-    z64* buf = nullptr;
-    GC_HIP(hipMalloc(reinterpret_cast<void**>(&buf), (size_t)4 * D * sizeof(z64)));
-    struct Free {
-      z64* p;
-      ~Free() { (void)hipFree(p); }
-    } fr{buf};
+    // the whole dense state is built in the ctx's dense region (validation-sized)
+    z64* buf = reinterpret_cast<z64*>(ctx->ws + ctx->lay.off_dense);
     statevector_impl(ctx, buf, buf + D);
     z64 v;
     GC_HIP(hipMemcpy(&v, buf + y, sizeof(z64), hipMemcpyDeviceToHost));
@@ -715,7 +721,9 @@ int32_t gcamps_get_kernel_stats(gcamps_ctx* ctx, double out[8]) {
   return guarded(ctx, [&] {
     GC_CHECK(ctx && out, GCAMPS_EINVAL, "null argument");
     ctx->settle_mpo();
-    for (int i = 0; i < 8; ++i) out[i] = ctx->kstats[i];
+    for (int i = 0; i < 6; ++i) out[i] = ctx->kstats[i];
+    out[6] = ctx->stats_red[0];
+    out[7] = ctx->stats_red[2] > 0 ? ctx->stats_red[1] / ctx->stats_red[2] : 0.0;
   });
 }
 

@@ -20,7 +20,8 @@ struct Layout {
   int nslots;
   size_t off_slots, off_theta, off_G, off_U, off_Z, off_Utmp, off_B, off_B2, off_sig2, off_sig, off_lam,
       off_perm, off_eigG, off_eigV, off_flags, off_s2, off_s2w, off_wlist, off_partial, off_nbuf, nbuf_bytes, off_q64, off_q32,
-      off_rtab, off_qinv, off_tab, off_target, off_weyl, off_err, off_status, off_luts, off_sites, total;
+      off_rtab, off_qinv, off_tab, off_target, off_weyl, off_err, off_status, off_luts, off_sites, off_dense,
+      dense_dim, off_pcst, total;
 };
 
 Layout make_layout(const gcamps_config& c);
@@ -96,6 +97,7 @@ struct gcamps_ctx {
   uint32_t* dluts = nullptr;
   DevWeyl* weyl = nullptr;
   DevStatus* st = nullptr;
+  PcState* pcst = nullptr;  // rank-reduction state (device)
   z64 *theta = nullptr, *G = nullptr, *U = nullptr, *Z = nullptr, *Utmp = nullptr, *B = nullptr, *B2 = nullptr;
   double *sig2 = nullptr, *sig = nullptr, *lam = nullptr, *s2 = nullptr, *s2w = nullptr, *partial = nullptr;
   void* nbuf = nullptr;
@@ -134,6 +136,10 @@ struct gcamps_ctx {
   // [2] their device ms (Gram to truncation rule, second pass included), [3] MPO site launches,
   // [4] MPO bytes (each site tensor read once and its product written once), [5] MPO device ms
   double kstats[8] = {0};
+  // rank reduction of the rotated-tensor splits: [0] reduced factorisations, [1] their summed
+  // basis sizes r, [2] their summed sides m, [3] attempts that fell back to the full basis
+  double stats_red[4] = {0};
+  int last_basis = 0;  // singular values resolved by the last factorisation (m, or r when reduced)
   // gradient: recording and frozen replay (all null in ordinary use)
   std::vector<int32_t>* rank_rec = nullptr;          // kept rank of every factorisation
   std::vector<GateRec>* gate_rec = nullptr;          // Weyl string of every non-Clifford gate
@@ -182,22 +188,74 @@ struct gcamps_ctx {
   // Split M (p x q, row-major) into L (p x k) R (k x q).  mode 0: truncation rule with
   // renormalisation; mode 1: exact (rank floor only).  left_ortho: L has orthonormal columns
   // (else R has orthonormal rows).  Returns the status block of the final pass.
-  DevStatus factorize(const z64* M, int p, int q, int mode, int left_ortho, z64* Lout, z64* Rout) {
+  // reduce: the split of a rotated two-site tensor, whose Gram is often of rank far below m; the
+  // eigensolver then runs on the r x r matrix of a pivoted Cholesky reduction (mode 0 with a
+  // positive cutoff, outside gradient recording and replay).
+  DevStatus factorize(const z64* M, int p, int q, int mode, int left_ortho, z64* Lout, z64* Rout,
+                      bool reduce = false) {
     const bool wide = p <= q;
     const int m = wide ? p : q, kW = wide ? q : p;
     GC_CHECK((size_t)m <= lay.mcap && (size_t)m * kW <= lay.slot_elems, GCAMPS_ECAPACITY,
              "factorisation exceeds workspace capacity");
     const z64 one = {1.0, 0.0};
     GC_HIP(hipEventRecord(evf0, stream));
+    auto gram = [&]() {
+      if (wide)
+        launch_zgemm(stream, 0, 1, m, m, q, M, q, M, q, G, m, one, 0, 1);
+      else
+        launch_zgemm(stream, 1, 0, m, m, p, M, q, M, q, G, m, one, 0, 1);
+    };
+    gram();
+    // basis: nb columns of U (ld ldu); tail: weight outside the basis, always discarded
+    int nb = m, ldu = m;
+    const double* tail = nullptr;
+    const bool try_reduce = reduce && mode == 0 && cfg.cutoff > 0.0 && m > kSmallEig && !tape && !rank_rec &&
+                            !rank_frz;
+    bool reduced = false;
+    if (try_reduce) {
+      // stop once the Schur complement's trace is below min(1e-14, cutoff / 2m) of the trace: then
+      // its directions hold less than the cutoff even all together, and no eigenvalue moves by
+      // more than the Gram's own rounding
+      const double tol_rel = std::min(1e-14, cfg.cutoff / (2.0 * m));
+      const int rmax = (3 * m) / 4;
+      PcState hs{};
+      const int r = pchol_reduce(stream, G, m, m, Z, m, tol_rel, rmax, sig, perm, pcst, &hs);
+      if (hs.done && r >= 1 && r <= rmax) {
+        // H = L^H L = Y lam Y^H with relative accuracy, so that the columns of L Y are
+        // orthogonal to ~1e-14 of their norms even where lam is tiny (an absolute criterion
+        // leaves them off by ~tr H / lam times that)
+        launch_zgemm(stream, 1, 0, r, r, m, Z, m, Z, m, Utmp, r, one, 0, 1);
+        eig_hermitian(stream, Utmp, r, r, G, r, lam, 1, eig, st, nullptr);
+        launch_zgemm(stream, 0, 0, m, r, r, Z, m, G, r, U, r, one, 0, 0);     // L Y
+        launch_normalize_cols(stream, U, m, r, r);
+        orthonormalize_cols(stream, U, Z, Utmp, m, r, 2);
+        nb = r;
+        ldu = r;
+        tail = &pcst->tres;
+        reduced = true;
+        stats_red[0] += 1;
+        stats_red[1] += r;
+        stats_red[2] += m;
+      } else {
+        gram();  // no useful reduction: the full eigen-decomposition of the (recomputed) Gram
+        stats_red[3] += 1;
+      }
+    }
+    if (!reduced) eig_hermitian(stream, G, m, m, U, m, lam, 0, eig, st, nullptr);
     if (wide)
-      launch_zgemm(stream, 0, 1, m, m, q, M, q, M, q, G, m, one, 0, 1);
+      launch_zgemm(stream, 1, 0, nb, q, m, U, ldu, M, q, B, q, one, 0, 0);
     else
-      launch_zgemm(stream, 1, 0, m, m, p, M, q, M, q, G, m, one, 0, 1);
-    eig_hermitian(stream, G, m, m, U, m, lam, 0, eig, st, nullptr);
-    if (wide)
-      launch_zgemm(stream, 1, 0, m, q, m, U, m, M, q, B, q, one, 0, 0);
-    else
-      launch_zgemm(stream, 1, 1, m, p, m, U, m, M, q, B, p, one, 0, 0);
+      launch_zgemm(stream, 1, 1, nb, p, m, U, ldu, M, q, B, p, one, 0, 0);
+    if (reduced) {
+      // Rayleigh-Ritz on the reduced basis: B B^H = U^H G U with the full Gram, so its
+      // eigenvalues err by the square of the basis error where L L^H's err by tr S
+      launch_zgemm(stream, 0, 1, nb, nb, kW, B, kW, B, kW, G, nb, one, 0, 1);
+      eig_hermitian(stream, G, nb, nb, Z, nb, lam, 0, eig, st, nullptr);
+      launch_zgemm(stream, 0, 0, m, nb, nb, U, ldu, Z, nb, Utmp, ldu, one, 0, 0);
+      std::swap(U, Utmp);
+      launch_zgemm(stream, 1, 0, nb, kW, nb, Z, nb, B, kW, B2, kW, one, 0, 0);
+      std::swap(B, B2);
+    }
     // recorded decision: kept rank in the low bits, bit 30 = the accurate second pass ran
     int force_k = 0, force_pass2 = -1;
     if (rank_frz) {
@@ -206,28 +264,28 @@ struct gcamps_ctx {
       force_k = v & kRankMask;
       force_pass2 = (v >> kPass2Bit) & 1;
     }
-    launch_rownorm2(stream, B, m, kW, kW, sig2);
-    launch_trunc(stream, sig2, m, cfg.cutoff, cfg.chi_max, mode, force_k, perm, sig, st);
+    launch_rownorm2(stream, B, nb, kW, kW, sig2);
+    launch_trunc(stream, sig2, nb, cfg.cutoff, cfg.chi_max, mode, force_k, perm, sig, st, tail);
     GC_HIP(hipEventRecord(evf1, stream));
     DevStatus h;
     read_status(h);
-    GC_CHECK(m > kSmallEig || h.converged, GCAMPS_ENUMERIC, "eigensolver did not converge");
+    GC_CHECK(nb > kSmallEig || h.converged, GCAMPS_ENUMERIC, "eigensolver did not converge");
     stats[5] += 8.0 * (double)m * m * kW * 2.0;
     const bool pass2 = force_pass2 >= 0 ? force_pass2 == 1 : h.need_pass2 != 0;
     if (pass2) {
       // accurate second pass on the nearly diagonal Gram of B (relative criterion)
-      launch_zgemm(stream, 0, 1, m, m, kW, B, kW, B, kW, G, m, one, 0, 1);
-      eig_hermitian(stream, G, m, m, Z, m, lam, 1, eig, st, nullptr);
-      launch_zgemm(stream, 0, 0, m, m, m, U, m, Z, m, Utmp, m, one, 0, 0);
+      launch_zgemm(stream, 0, 1, nb, nb, kW, B, kW, B, kW, G, nb, one, 0, 1);
+      eig_hermitian(stream, G, nb, nb, Z, nb, lam, 1, eig, st, nullptr);
+      launch_zgemm(stream, 0, 0, m, nb, nb, U, ldu, Z, nb, Utmp, ldu, one, 0, 0);
       std::swap(U, Utmp);
-      launch_zgemm(stream, 1, 0, m, kW, m, Z, m, B, kW, B2, kW, one, 0, 0);
+      launch_zgemm(stream, 1, 0, nb, kW, nb, Z, nb, B, kW, B2, kW, one, 0, 0);
       std::swap(B, B2);
-      launch_rownorm2(stream, B, m, kW, kW, sig2);
-      launch_trunc(stream, sig2, m, cfg.cutoff, cfg.chi_max, mode, force_k, perm, sig, st);
+      launch_rownorm2(stream, B, nb, kW, kW, sig2);
+      launch_trunc(stream, sig2, nb, cfg.cutoff, cfg.chi_max, mode, force_k, perm, sig, st, tail);
       GC_HIP(hipEventRecord(evf1, stream));
       read_status(h);
-      GC_CHECK(m > kSmallEig || h.converged, GCAMPS_ENUMERIC, "eigensolver did not converge (second pass)");
-      stats[5] += 8.0 * (double)m * m * kW * 2.0;
+      GC_CHECK(nb > kSmallEig || h.converged, GCAMPS_ENUMERIC, "eigensolver did not converge (second pass)");
+      stats[5] += 8.0 * (double)nb * nb * kW * 2.0;
     }
     GC_CHECK(std::isfinite(h.eps) && h.kept >= 1, GCAMPS_ENUMERIC, "factorisation produced non-finite values");
     {  // both events have completed: read_status synchronised the stream after evf1
@@ -258,8 +316,9 @@ struct gcamps_ctx {
       GC_HIP(hipMemcpyAsync(f.sig, sig, m * sizeof(double), hipMemcpyDeviceToDevice, stream));
       GC_HIP(hipMemcpyAsync(f.perm, perm, m * sizeof(int), hipMemcpyDeviceToDevice, stream));
     }
-    launch_emit(stream, wide ? 1 : 0, left_ortho, mode == 0 ? 1 : 0, p, q, h.kept, U, m, B, kW, perm, sig, Lout,
+    launch_emit(stream, wide ? 1 : 0, left_ortho, mode == 0 ? 1 : 0, p, q, h.kept, U, ldu, B, kW, perm, sig, Lout,
                 Rout);
+    last_basis = nb;
     return h;
   }
 
@@ -662,7 +721,7 @@ struct gcamps_ctx {
             op.chil = cl;
             op.chir = cr;
           }
-          h = factorize(theta, cl * d, d * cr, 0, ltr ? 1 : 0, Lbuf, Rbuf);
+          h = factorize(theta, cl * d, d * cr, 0, ltr ? 1 : 0, Lbuf, Rbuf, true);
           if (tape) {
             op.f = last_fact;
             op.cstar = h.cstar;

@@ -87,6 +87,8 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 constexpr int kMaxD = 7;
 constexpr int kMaxGateTerms = 81;  // Weyl terms of a general gate (two qutrits: 3^4)
 constexpr int kMaxN = 128;
+constexpr double kNearTieLowp = 1e-4;  // smallest re-score window with FP32 / split-BF16 scoring
+constexpr size_t kDenseMax = size_t(1) << 16;  // largest d^n of the dense (validation) state
 constexpr int kSmallEig = 32;   // largest m handled by the single-workgroup eigensolver
 constexpr int kBlk = 16;        // block size of the multi-workgroup block Jacobi
 

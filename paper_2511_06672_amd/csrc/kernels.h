@@ -37,14 +37,34 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
 void launch_rownorm2(hipStream_t s, const z64* B, int m, int k, int ldb, double* out);
 // Sort, truncation rule, pass-2 decision.  mode 0 = truncate (cutoff, chi_max), 1 = floor only;
 // force_k > 0 keeps exactly that rank (frozen-decision replay).
+// extra (nullable, device): weight of directions outside sig2 that are discarded whatever the
+// rule (a rank reduction's remainder), added to every tail sum and to the total.
 void launch_trunc(hipStream_t s, const double* sig2, int m, double cutoff, int chi_max, int mode,
-                  int force_k, int* perm, double* sig_sorted, DevStatus* st);
+                  int force_k, int* perm, double* sig_sorted, DevStatus* st, const double* extra = nullptr);
 // Write the two factors (see kernels_linalg.hip for the case table).
 void launch_emit(hipStream_t s, int wide, int left_ortho, int renorm, int p, int q, int kept,
                  const z64* U, int ldu, const z64* B, int ldb, const int* perm, const double* sig,
                  z64* L, z64* R);
 void launch_copy(hipStream_t s, z64* dst, const z64* src, size_t count);
 void launch_fill_identity(hipStream_t s, z64* U, int m, int ld);
+
+// ------------------------------------------------------------------ rank reduction (kernels_reduce.hip)
+// Pivoted Cholesky of the Hermitian PSD G (m x m, ld ldg; destroyed: it ends as the Schur
+// complement): G = L L^H + S with L (m x r, ld ldl) and tr S <= tol_rel * tr G, or r = rmax
+// columns without meeting the bound (then *host_state.done == 0).  dvec (m doubles) and pv
+// (m ints) are scratch; stt is a device PcState.  Returns r; host_state receives the final state
+// (tres = tr S).
+struct PcState {
+  int32_t r, done, pad0, pad1;
+  double trace, tres;
+};
+int pchol_reduce(hipStream_t s, z64* G, int m, int ldg, z64* L, int ldl, double tol_rel, int rmax, double* dvec,
+                 int* pv, PcState* stt, PcState* host_state);
+// Columns of X (m x r, ld ldx) scaled to unit 2-norm.
+void launch_normalize_cols(hipStream_t s, z64* X, int m, int r, int ldx);
+// X (m x r, ld r) replaced by its polar factor by `iters` Newton-Schulz steps (X nearly
+// orthonormal); Xn (m x r) and S (r x r) are scratch.
+void orthonormalize_cols(hipStream_t s, z64* X, z64* Xn, z64* S, int m, int r, int iters);
 
 // ------------------------------------------------------------------ MPS kernels (kernels_mps.hip)
 struct MpoCoeff {

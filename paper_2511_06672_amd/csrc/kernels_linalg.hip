@@ -701,7 +701,8 @@ __global__ void k_rownorm2(const z64* __restrict__ B, int m, int k, int ldb, dou
 constexpr int TRUNC_MAX = 4096;
 __global__ __launch_bounds__(1024) void k_trunc(const double* __restrict__ sig2, int m, double cutoff, int chi_max,
                                                 int mode, int force_k, int* __restrict__ perm,
-                                                double* __restrict__ sig_sorted, DevStatus* st) {
+                                                double* __restrict__ sig_sorted, DevStatus* st,
+                                                const double* __restrict__ extra) {
   __shared__ double key[TRUNC_MAX];
   __shared__ int idx[TRUNC_MAX];
   int P2 = 1;
@@ -739,10 +740,12 @@ __global__ __launch_bounds__(1024) void k_trunc(const double* __restrict__ sig2,
     sig_sorted[i] = sqrt(key[i]);
   }
   if (t == 0) {
-    double total = 0.0;
+    // weight outside the listed values (always discarded): starts every tail
+    const double ex = extra ? fmax(*extra, 0.0) : 0.0;
+    double total = ex;
     for (int i = m - 1; i >= 0; --i) total += key[i];
     // smallest k with tail[k] <= cutoff, tails accumulated from the smallest value
-    double tails_k = 0.0;
+    double tails_k = ex / total;
     int kcut = m;
     for (int k = m - 1; k >= 1; --k) {
       tails_k += key[k] / total;
@@ -778,7 +781,7 @@ __global__ __launch_bounds__(1024) void k_trunc(const double* __restrict__ sig2,
       k = force_k < m ? force_k : m;
       flagged = 0;
     }
-    double eps = 0.0;
+    double eps = ex / total;
     for (int i = m - 1; i >= k; --i) eps += key[i] / total;
     st->kept = k;
     st->eps = eps;
@@ -981,10 +984,10 @@ void launch_rownorm2(hipStream_t s, const z64* B, int m, int k, int ldb, double*
 }
 
 void launch_trunc(hipStream_t s, const double* sig2, int m, double cutoff, int chi_max, int mode, int force_k,
-                  int* perm, double* sig_sorted, DevStatus* st) {
+                  int* perm, double* sig_sorted, DevStatus* st, const double* extra) {
   GC_CHECK(m <= TRUNC_MAX, GCAMPS_ECAPACITY, "truncation: matrix side exceeds 4096");
   hipLaunchKernelGGL(k_trunc, dim3(1), dim3(1024), 0, s, sig2, m, cutoff, chi_max, mode, force_k, perm, sig_sorted,
-                     st);
+                     st, extra);
   GC_LAUNCH_CHECK();
 }
 

@@ -20,6 +20,7 @@ GCAMPS_OK = 0
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EWORKSPACE", -4: "ECAPACITY",
                 -5: "EDEVICE", -6: "ENUMERIC"}
 SCORE_FP64, SCORE_FP32, SCORE_BF16, SCORE_REPLICA = 0, 1, 2, 3
+FACTORIZE_REDUCE = 1
 WORDS_DISENTANGLERS, WORDS_ALL = 0, 1
 CRITERION_RENYI2, CRITERION_BOND_DIM = 0, 1
 
@@ -95,7 +96,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gcamps_candset_destroy": [P],
         "gcamps_set_candset": [P, P],
         "gcamps_score_bond": [P, I32, C.POINTER(D), I64],
-        "gcamps_factorize": [P, C.POINTER(D), I32, I32, C.POINTER(D), C.POINTER(I32), C.POINTER(D),
+        "gcamps_factorize": [P, C.POINTER(D), I32, I32, I32, C.POINTER(D), C.POINTER(I32), C.POINTER(D),
                              C.POINTER(D), C.POINTER(D)],
         "gcamps_clifford_words": [I32, I32, C.POINTER(I32), I32, C.POINTER(C.c_uint8), I64, C.POINTER(I32),
                                   C.POINTER(I64)],
@@ -270,10 +271,11 @@ class State:
         _check(lib().gcamps_score_bond(self.handle, bond, buf, cnt))
         return np.frombuffer(buf, dtype=np.float64).copy()
 
-    def factorize(self, m, factors: bool = False):
+    def factorize(self, m, factors: bool = False, reduce: bool = False):
         """The split's factorisation of a host matrix m (p x q complex) under this ctx's
-        truncation rule (gcamps_factorize).  Returns (singular values in descending order,
-        kept rank, discarded weight, L, R); L (p x kept) and R (kept x q) only with factors,
+        truncation rule (gcamps_factorize; ``reduce`` selects the rank-reduced path of the
+        splits after a disentangler).  Returns (singular values in descending order, kept
+        rank, discarded weight, L, R); L (p x kept) and R (kept x q) only with factors,
         else None."""
         m = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
         p, q = m.shape
@@ -283,8 +285,8 @@ class State:
         lbuf = np.zeros(p * mn, dtype=np.complex128) if factors else None
         rbuf = np.zeros(mn * q, dtype=np.complex128) if factors else None
         dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None  # noqa: E731
-        _check(lib().gcamps_factorize(self.handle, dp(m), p, q, dp(sig), C.byref(kept), C.byref(eps), dp(lbuf),
-                                      dp(rbuf)))
+        _check(lib().gcamps_factorize(self.handle, dp(m), p, q, FACTORIZE_REDUCE if reduce else 0, dp(sig),
+                                      C.byref(kept), C.byref(eps), dp(lbuf), dp(rbuf)))
         k = kept.value
         L = lbuf[:p * k].reshape(p, k) if factors else None
         R = rbuf[:k * q].reshape(k, q) if factors else None
@@ -356,7 +358,8 @@ class State:
         """Compression and MPO counters (gcamps_get_kernel_stats)."""
         out = (C.c_double * 8)()
         _check(lib().gcamps_get_kernel_stats(self.handle, out))
-        keys = ["factorisations", "factor_svd_flops", "factor_ms", "mpo_launches", "mpo_bytes", "mpo_ms"]
+        keys = ["factorisations", "factor_svd_flops", "factor_ms", "mpo_launches", "mpo_bytes", "mpo_ms",
+                "reduced", "reduced_basis_frac"]
         return dict(zip(keys, list(out)))
 
     def stats(self) -> dict:

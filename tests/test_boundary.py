@@ -40,6 +40,29 @@ def test_workspace_sizing_and_validation():
         assert e.value.code == -1
 
 
+def test_near_tie_floor_of_the_low_precision_modes():
+    """FP32 and split-BF16 scoring need a re-score window of at least 1e-4 (twice their
+    measured S2 error and more), so that the FP64 choice always lies inside it; replica
+    scoring is FP64 arithmetic and keeps the 1e-6 floor; FP64 scoring ignores the field."""
+    for prec in (g.SCORE_FP32, g.SCORE_BF16):
+        assert g.workspace_bytes(g.make_config(3, 8, 16, 0.0, score_prec=prec, near_tie=1e-4)) > 0
+        with pytest.raises(g.GcampsError) as e:
+            g.workspace_bytes(g.make_config(3, 8, 16, 0.0, score_prec=prec, near_tie=9.9e-5))
+        assert e.value.code == -1
+    assert g.workspace_bytes(g.make_config(3, 8, 16, 0.0, score_prec=g.SCORE_REPLICA, near_tie=1e-6)) > 0
+    assert g.workspace_bytes(g.make_config(3, 8, 16, 0.0, score_prec=g.SCORE_FP64, near_tie=0.0)) > 0
+
+
+def test_dense_region_is_counted_only_for_small_states():
+    """The amplitude call builds the dense state inside the ctx workspace (4 complex128 plus
+    an 8 + n byte table per index) whenever d^n <= 2^16, so it needs no allocation."""
+    def ws(d, n):
+        return g.workspace_bytes(g.make_config(d, n, 4, 0.0))
+    # qubits: 2^16 has the region, 2^17 does not; the difference dominates everything else
+    assert ws(2, 16) - ws(2, 17) > (1 << 16) * (64 + 8 + 16) - (1 << 20)
+    assert ws(2, 16) >= (1 << 16) * (64 + 8 + 16)
+
+
 def test_replica_mode_sizing_and_validation():
     """Replica scoring: d = 2, 3 only; its workspace holds the candidate tables
     (2 * N_c * d^8 complex128) and scratch for the Gram of Theta over chi_max d^2 rows."""
@@ -94,7 +117,8 @@ def test_struct_layouts_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     fields = {
         "gcamps_config": (g.Config, ["d", "n", "chi_max", "cutoff", "score_prec", "near_tie", "tie_tol",
-                                     "max_sweeps", "auto_disentangle", "max_candidates"]),
+                                     "max_sweeps", "auto_disentangle", "max_candidates", "max_gate_terms",
+                                     "criterion"]),
         "gcamps_word": (g.CWord, ["len", "gens", "weyl"]),
         "gcamps_op": (g.COp, ["kind", "count", "sites", "words", "phi"]),
         "gcamps_batch_item": (g.CBatchItem, ["cfg", "ops", "n_ops", "status", "fidelity", "bond_dims",

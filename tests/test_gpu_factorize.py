@@ -18,6 +18,15 @@ With cutoff 0 the rank floor decides, through the relative-accuracy second pass:
 rank-50 matrix keeps 50 with its null values below the floor, and a graded spectrum
 sigma_i = 10^(-0.3 i) keeps 44 (values down to 1.3e-13 sigma_0), checked against the
 constructed spectrum itself.
+
+The rank-reduced path (GCAMPS_FACTORIZE_REDUCE, used for the splits after a disentangler) is held
+to the same bars: a pivoted Cholesky factorisation of the Gram stops once the remaining trace is
+below min(1e-14, cutoff / 2m) of the whole, so every singular value it leaves out has
+sigma^2 <= 5.6e-14 sigma_0^2 m here, inside the 1e-11 sigma_0^2 bar, and the remainder is counted
+as discarded weight (inside the 1e-12 absolute bar).  Cases: exact rank m/3 (the shape of a
+rotated two-site tensor at chi = 256: 768 x 768, rank 256), rank plus noise below the bound, a
+decaying spectrum cut by the cutoff inside the reduced basis, and a full-rank matrix, where the
+reduction gives nothing and the full path must run.
 """
 import sys
 
@@ -52,14 +61,14 @@ def gauss(rng, p, q):
     return (rng.standard_normal((p, q)) + 1j * rng.standard_normal((p, q))) / np.sqrt(2)
 
 
-def check(g, st, m, cutoff, factors):
-    sig, k, eps, L, R = st.factorize(m, factors=factors)
+def check(g, st, m, cutoff, factors, reduce=False, kept_tol=1e-12):
+    sig, k, eps, L, R = st.factorize(m, factors=factors, reduce=reduce)
     ref = np.linalg.svd(m, compute_uv=False)
     kr, er, _ = rtrunc(ref, cutoff, CHI)
     s0 = ref[0]
     assert k == kr
     assert np.all(np.diff(sig) <= 0)
-    assert np.max(np.abs(sig[:k] - ref[:k])) <= 1e-12 * s0
+    assert np.max(np.abs(sig[:k] - ref[:k])) <= kept_tol * s0
     assert np.max(np.abs(sig ** 2 - ref ** 2)) <= 1e-11 * s0 ** 2
     assert abs(eps - er) <= max(1e-9 * er, 1e-12)
     if factors:
@@ -105,6 +114,53 @@ def test_factorize_graded_spectrum_second_pass(g):
     assert np.max(np.abs(sig[:k] - true[:k])) <= 2e-14
     assert np.max(np.abs(L.conj().T @ L - np.eye(k))) <= 1e-12
     assert abs(eps - np.sum(true[k:] ** 2) / np.sum(true ** 2)) <= 1e-15
+
+
+@pytest.mark.parametrize("p,q,r", [(768, 768, 256), (243, 729, 81), (729, 243, 81), (96, 96, 40)])
+def test_factorize_reduced_exact_rank(g, p, q, r):
+    say(f"factorize reduced, exact rank {r} in {p} x {q}")
+    rng = np.random.default_rng(500 + p + q + r)
+    m = gauss(rng, p, r) @ gauss(rng, r, q) / np.sqrt(r)
+    st = state(g, CUT)
+    k, sig, s0 = check(g, st, m, CUT, factors=True, reduce=True)
+    assert k == r
+    ks = st.kernel_stats()
+    assert ks["reduced"] == 1 and ks["reduced_basis_frac"] <= (r + 16) / min(p, q)
+
+
+def test_factorize_reduced_noise_and_decaying_spectrum(g):
+    rng = np.random.default_rng(501)
+    say("factorize reduced, rank 200 plus 1e-9 noise, 900 x 1200")
+    m = gauss(rng, 900, 200) @ gauss(rng, 200, 1200) / np.sqrt(200) + 1e-9 * gauss(rng, 900, 1200)
+    assert check(g, state(g, CUT), m, CUT, factors=True, reduce=True)[0] == 200
+    # sigma_i = 10^(-0.047 i): the tail after k values is 10^(-0.094 k), so the cutoff falls
+    # between k = 106 (tail 1.1e-10) and k = 107 (0.87e-10), away from either
+    say("factorize reduced, sigma_i = 10^(-0.047 i) on 600 x 600 (the cutoff cuts inside the basis)")
+    u, _, _ = svd(gauss(rng, 600, 600))
+    v, _, _ = svd(gauss(rng, 600, 600))
+    true = 10.0 ** (-0.047 * np.arange(600))
+    m = (u * true) @ v.conj().T
+    ref = np.linalg.svd(m, compute_uv=False)
+    # Kept values reach 1e-5 sigma_0 here, where a Gram's absolute eigenvalue error (~1e-16
+    # sigma_0^2) is ~1e-11 sigma_0 in sigma: the reduced path must be as accurate as the full one
+    full = state(g, CUT)
+    sf, kf, _, _, _ = full.factorize(m)
+    err_full = np.max(np.abs(sf[:kf] - ref[:kf]))
+    st = state(g, CUT)
+    k, sig, s0 = check(g, st, m, CUT, factors=True, reduce=True, kept_tol=max(1e-12, 4 * err_full))
+    err_red = np.max(np.abs(sig[:k] - ref[:k]))
+    say(f"  kept sigma error: reduced {err_red:.2e}, full {err_full:.2e} (sigma_0 = {s0:.3f})")
+    assert k == kf == 107
+    assert st.kernel_stats()["reduced"] == 1
+
+
+def test_factorize_reduced_falls_back_on_full_rank(g):
+    say("factorize reduced on a full-rank 400 x 500 gaussian (falls back to the full basis)")
+    rng = np.random.default_rng(502)
+    st = state(g, CUT)
+    k, _, _ = check(g, st, gauss(rng, 400, 500), CUT, factors=True, reduce=True)
+    assert k == 400
+    assert st.kernel_stats()["reduced"] == 0
 
 
 def test_factorize_maximum_size(g):

@@ -2,8 +2,14 @@
 
 * No truncation (chi_max = d^(n/2), cutoff 0): the GCAMPS state is the exact state, so the
   gradient must equal the dense derivative (oracle.gradient.dense_gradient).
-* Truncated regime: the derivative with frozen decisions; compared with Richardson-
+* The n = 8 copy of the differentiation workload at its own settings (chi_max = 256, cutoff
+  1e-10, its 512 candidates, FP64 scoring): nothing above the cutoff is truncated at n = 8, so
+  again the dense derivative, on all 64 angles.
+* Truncated regime: the derivative with frozen decisions; compared on all angles with the
+  oracle's own reverse-mode derivative (oracle/adjoint.py) and on a sample with Richardson-
   extrapolated central differences of the oracle's frozen replay and of the library's own.
+* Full size (n = 24): adjoint against the library's own frozen replay on nine angles spread
+  over |g| (the largest, the median, the smallest and six between).
 Tolerances: relative to the largest component (infinity norm); central differences with
 step h carry an O(h^2) error plus the replay's rounding divided by h.
 """
@@ -82,6 +88,48 @@ def test_gradient_with_truncation_matches_oracle_finite_differences():
     gr.close()
 
 
+def test_gradient_n8_copy_at_the_differentiation_settings():
+    from oracle.gradient import dense_gradient
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import workload
+    wl = workload("grad_d3_n24", n=8)                  # same recipe: 16 layers, 32 gates, 512 candidates
+    c = wl.circuit
+    th = theta_of(c)
+    dense = dense_gradient(c, th)
+    assert np.max(np.abs(dense)) > 1e-2
+    print("[gpu-case] gradient n=8 copy, chi_max=256, 512 candidates", flush=True)
+    cfg = g.make_config(3, 8, wl.chi_max, wl.cutoff, score_prec=0, max_candidates=len(wl.candidates))
+    gr = g.Gradient(cfg, c, g.CandSet(3, wl.candidates), th)
+    _, grad = gr.gradient(th)
+    err = rel_inf(grad, dense)
+    print(f"[gpu-case] n=8 copy: |g - dense|_inf / |dense|_inf = {err:.2e}", flush=True)
+    assert err < EXACT_TOL
+    gr.close()
+
+
+def test_gradient_with_truncation_matches_the_oracle_adjoint():
+    from oracle.adjoint import frozen_adjoint
+    from oracle.gcamps import Config
+    from oracle.gradient import record
+    from paper_2511_06672_amd import gcamps as g
+    from paper_2511_06672_amd.workload import candidate_words, workload
+    c = workload("grad_d3_n24", n=8).circuit
+    th = theta_of(c)
+    cands = candidate_words(3, 24, 903)
+    ocfg = Config(chi_max=9, cutoff=1e-10)
+    st, frozen = record(c, cands, ocfg, th)
+    assert st.f_est < 0.999
+    loss_o, grad_o, _, _ = frozen_adjoint(c, cands, ocfg, th, frozen)
+    print("[gpu-case] gradient truncated regime n=8 chi=9 against the oracle adjoint", flush=True)
+    gr = g.Gradient(g.make_config(3, 8, 9, 1e-10, max_candidates=24), c, g.CandSet(3, cands), th)
+    loss, grad = gr.gradient(th)
+    assert abs(loss - loss_o) < 1e-10
+    err = rel_inf(grad, grad_o)
+    print(f"[gpu-case] truncated n=8: |g - oracle adjoint|_inf / |.|_inf = {err:.2e}", flush=True)
+    assert err < FD_TOL
+    gr.close()
+
+
 def test_gradient_with_fixed_gates_and_single_site_support():
     """T gates with fixed angles mixed with parametrised ones; a support of one site
     (the first gate acts on |0>, where Z_s commutes through the identity Clifford)."""
@@ -104,27 +152,38 @@ def test_gradient_with_fixed_gates_and_single_site_support():
     gr.close()
 
 
-def test_gradient_full_size_against_finite_differences():
+@pytest.fixture(scope="module")
+def full_size():
     """The gradient workload at full size (n = 24, 48 layers, 32 gates, chi_max = 256, 512
-    candidates, FP64 scoring), in the configuration the benchmark times.  The oracle cannot
-    replay it in test time, so the property checked is adjoint = derivative of the library's
-    own frozen replay, by Richardson-extrapolated central differences with h = 3e-5 on the
-    largest component and one more.  Tolerance 2e-5 of |g|_inf: the replay's rounding
-    (~1e-13 absolute in L) over 2h gives ~3e-9 absolute, ~6e-6 of |g|_inf ~ 5e-4."""
+    candidates, FP64 scoring), in the configuration the benchmark times: recorded, then one
+    reverse sweep."""
     from paper_2511_06672_amd import gcamps as g
     from paper_2511_06672_amd.workload import workload
     wl = workload("grad_d3_n24")
     c = wl.circuit
     th = theta_of(c)
-    print("[gpu-case] gradient full size n=24 chi=256: record", flush=True)
+    print("[gpu-case] gradient full size n=24 chi=256: record and reverse sweep", flush=True)
     cfg = g.make_config(3, c.n, wl.chi_max, wl.cutoff, score_prec=0, max_candidates=len(wl.candidates))
     gr = g.Gradient(cfg, c, g.CandSet(3, wl.candidates), th)
-    print("[gpu-case] gradient full size: reverse sweep", flush=True)
     loss, grad = gr.gradient(th)
     assert loss == gr.loss0
+    order = [int(k) for k in np.argsort(-np.abs(grad))]
+    # nine angles spread over |g|: the largest, the median, the smallest and six between
+    picks = [order[int(round(f * (len(order) - 1)))] for f in (0.0, 0.1, 0.2, 0.35, 0.5, 0.65, 0.8, 0.9, 1.0)]
+    yield gr, th, grad, picks
+    gr.close()
+
+
+@pytest.mark.parametrize("part", [0, 1, 2])
+def test_gradient_full_size_against_finite_differences(full_size, part):
+    """Adjoint = derivative of the library's own frozen replay (the oracle cannot replay n = 24 in
+    test time), by Richardson-extrapolated central differences with h = 3e-5, on three of the
+    nine spread angles per part.  Tolerance 2e-5 of |g|_inf: the replay's rounding (~1e-13
+    absolute in L) over 2h gives ~3e-9 absolute, ~6e-6 of |g|_inf ~ 5e-4, and the O(h^4)
+    remainder is below that."""
+    gr, th, grad, picks = full_size
     gmax = np.max(np.abs(grad))
     assert gmax > 1e-5 and np.all(np.isfinite(grad))
-    order = np.argsort(-np.abs(grad))
     h = 3e-5
 
     def central(k, step):
@@ -132,8 +191,7 @@ def test_gradient_full_size_against_finite_differences():
         e[k] = step
         return (gr.loss(th + e) - gr.loss(th - e)) / (2 * step)
 
-    for k in (int(order[0]), int(order[7])):
-        print(f"[gpu-case] gradient full size: differences on parameter {k}", flush=True)
+    for k in picks[3 * part:3 * part + 3]:
+        print(f"[gpu-case] gradient full size: differences on parameter {k} (|g| = {abs(grad[k]):.2e})", flush=True)
         fd = (4 * central(k, h) - central(k, 2 * h)) / 3
         assert abs(fd - grad[k]) < 2e-5 * gmax
-    gr.close()
