@@ -253,6 +253,17 @@ int32_t gcamps_expectation(gcamps_ctx* ctx, const int8_t* x, const int8_t* z, in
 int32_t gcamps_statevector(gcamps_ctx* ctx, void* dev_out, void* dev_scratch,
                            size_t scratch_bytes);
 
+/* gcamps_statevector without any allocation and without a caller scratch buffer, for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The three dense work vectors live in a static device array of the
+ * library, 3 * 16 * 2^16 bytes (3 MiB), one copy per GPU held until the process ends; its
+ * device address is looked up by gcamps_init on the ctx's device.  Same result as
+ * gcamps_statevector, bit for bit.  Limit d^n <= 2^16.  Calls that overlap on one GPU share
+ * that array and race: run them one at a time per GPU.  dev_out: d^n complex128 (device).
+ * Nothing is allocated; the stream is synchronised.
+ * Errors: EINVAL (null pointer), EUNSUPPORTED (d^n > 2^16), EDEVICE. */
+int32_t gcamps_statevector_static(gcamps_ctx* ctx, void* dev_out);
+
 /* One amplitude <digits|psi> of psi = C|MPS> (§3), same global-phase convention
  * as gcamps_statevector.  For validation at small sizes (d^n <= 2^16): the dense
  * state is formed in the ctx's own workspace (4 * 16 * d^n bytes plus the

@@ -168,6 +168,28 @@ Layout make_layout(const gcamps_config& c) {
 }
 }  // namespace gc
 
+// Scratch of gcamps_statevector_static: the three dense work vectors of the largest dense state
+// (3 * 2^16 complex128, 3 MiB), one copy per GPU for the life of the process.  Host code never
+// passes the array's name to a kernel: it stands for the host-side shadow, not the device copy.
+// The device address of each GPU's copy is looked up once, with that GPU current, and kept.
+static __device__ __align__(256) z64 scratch[3 * kDenseMax];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_dev[kMaxDevices] = {nullptr};
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current GPU (looked up at gcamps_init, once per device).
+static void* scratch_address(int dev) {
+  GC_CHECK(dev >= 0 && dev < kMaxDevices, GCAMPS_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    GC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    GC_CHECK(ptr != nullptr, GCAMPS_EDEVICE, "no device address for the static scratch");
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
 // ------------------------------------------------------------------------------- C ABI
 extern "C" {
 
@@ -194,7 +216,11 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
       linalg_set_attributes();
       rank_set_attributes();
     });
+    int dev = 0;
+    GC_HIP(hipGetDevice(&dev));
+    void* sdev = scratch_address(dev);  // static scratch of gcamps_statevector_static on this GPU
     auto c = std::make_unique<gcamps_ctx>();
+    c->scratch_dev = sdev;
     c->cfg = *cfg;
     c->lay = lay;
     c->d = cfg->d;
@@ -636,6 +662,17 @@ int32_t gcamps_statevector(gcamps_ctx* ctx, void* dev_out, void* dev_scratch, si
     const long long D = dense_dim(ctx);
     GC_CHECK(scratch_bytes >= (size_t)3 * D * sizeof(z64), GCAMPS_EWORKSPACE, "scratch smaller than 3*16*d^n bytes");
     statevector_impl(ctx, reinterpret_cast<z64*>(dev_out), reinterpret_cast<z64*>(dev_scratch));
+  });
+}
+
+int32_t gcamps_statevector_static(gcamps_ctx* ctx, void* dev_out) {
+  return guarded(ctx, [&] {
+    GC_CHECK(ctx && dev_out, GCAMPS_EINVAL, "null argument");
+    const long long D = dense_dim(ctx);
+    GC_CHECK((size_t)D <= kDenseMax, GCAMPS_EUNSUPPORTED, "dense state above the static scratch (d^n <= 2^16)");
+    GC_CHECK(ctx->scratch_dev != nullptr, GCAMPS_EDEVICE, "static scratch not resolved for this ctx's device");
+    // every work vector is written before it is read (no part must start at zero)
+    statevector_impl(ctx, reinterpret_cast<z64*>(dev_out), reinterpret_cast<z64*>(ctx->scratch_dev));
   });
 }
 

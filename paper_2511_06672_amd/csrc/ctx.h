@@ -98,6 +98,7 @@ struct gcamps_ctx {
   DevWeyl* weyl = nullptr;
   DevStatus* st = nullptr;
   PcState* pcst = nullptr;  // rank-reduction state (device)
+  void* scratch_dev = nullptr;  // device address of the library's static scratch on this ctx's GPU
   z64 *theta = nullptr, *G = nullptr, *U = nullptr, *Z = nullptr, *Utmp = nullptr, *B = nullptr, *B2 = nullptr;
   double *sig2 = nullptr, *sig = nullptr, *lam = nullptr, *s2 = nullptr, *s2w = nullptr, *partial = nullptr;
   void* nbuf = nullptr;

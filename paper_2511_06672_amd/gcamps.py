@@ -29,7 +29,7 @@ SYMBOLS = [
     "gcamps_apply_clifford_layer", "gcamps_apply_phase_rotation", "gcamps_apply_gate", "gcamps_candset_create",
     "gcamps_candset_destroy", "gcamps_clifford_words", "gcamps_set_candset", "gcamps_score_bond",
     "gcamps_factorize", "gcamps_disentangle", "gcamps_expectation",
-    "gcamps_statevector", "gcamps_amplitude", "gcamps_get_tableau", "gcamps_get_bond_dims",
+    "gcamps_statevector", "gcamps_statevector_static", "gcamps_amplitude", "gcamps_get_tableau", "gcamps_get_bond_dims",
     "gcamps_get_fidelity", "gcamps_get_choice_log", "gcamps_get_site", "gcamps_get_stats",
     "gcamps_get_kernel_stats",
     "gcamps_batch_workspace_bytes", "gcamps_batch_run", "gcamps_grad_record", "gcamps_grad_loss",
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "gcamps_disentangle": [P, P, C.POINTER(I32), C.POINTER(I32)],
         "gcamps_expectation": [P, C.POINTER(C.c_int8), C.POINTER(C.c_int8), I32, C.POINTER(D)],
         "gcamps_statevector": [P, P, P, SZ],
+        "gcamps_statevector_static": [P, P],
         "gcamps_amplitude": [P, C.POINTER(C.c_int8), C.POINTER(D)],
         "gcamps_get_tableau": [P, C.POINTER(I32)],
         "gcamps_get_bond_dims": [P, C.POINTER(I32)],
@@ -312,6 +313,15 @@ class State:
         scratch = torch.empty(6 * D, dtype=torch.float64, device=self.device)
         _check(lib().gcamps_statevector(self.handle, C.c_void_p(out.data_ptr()),
                                         C.c_void_p(scratch.data_ptr()), scratch.numel() * 8))
+        v = out.cpu().numpy()
+        return v[0::2] + 1j * v[1::2]
+
+    def statevector_static(self) -> np.ndarray:
+        """gcamps_statevector_static: the dense state with the library's static scratch."""
+        import torch
+        D = self.d ** self.n
+        out = torch.empty(2 * D, dtype=torch.float64, device=self.device)
+        _check(lib().gcamps_statevector_static(self.handle, C.c_void_p(out.data_ptr())))
         v = out.cpu().numpy()
         return v[0::2] + 1j * v[1::2]
 
