@@ -33,7 +33,10 @@ A third measures the reverse-mode gradient of Re sum_j <Z_j> with respect to 64 
 angles (qutrits, n = 24, 48 layers, 32 parametrised gates, chi_max = 256, cutoff 1e-10,
 512 candidates, FP64 scoring):
 
-    python bench.py --workload grad
+    python bench.py --workload grad [--fd-angles all | lo:hi]
+
+With --fd-angles the line also carries the adjoint's largest error against Richardson-extrapolated
+central differences of the frozen replay (h = 3e-5) over those angles, relative to |g|_inf.
 
 A fourth runs the paper's own circuits (random Clifford layers, T on qudit 0; qutrits and
 qubits at N = 12 and 16, N layers) with the exhaustive disentanglers under the bond-dimension
@@ -354,6 +357,29 @@ def main_grad(args):
         log(f"gradient {k + 1}/{args.steps}: {times[-1]:.2f} s, |g|_inf {np.max(np.abs(grad)):.3e}")
     t = max(times)
     st = gr.stats()
+    fd_check = None
+    if args.fd_angles:
+        # adjoint against Richardson-extrapolated central differences of the frozen replay,
+        # (4 D(h) - D(2h)) / 3 with D(h) = (L(theta + h e_k) - L(theta - h e_k)) / 2h, h = 3e-5,
+        # on the angles of --fd-angles (lo:hi, or all); the error is normwise, relative to |g|_inf
+        lo, hi = (0, len(theta)) if args.fd_angles == "all" else map(int, args.fd_angles.split(":"))
+        h = 3e-5
+        gmax = float(np.max(np.abs(grad)))
+        worst, per = 0.0, {}
+        t0 = time.perf_counter()
+
+        def central(k, step):
+            e = np.zeros_like(theta)
+            e[k] = step
+            return (gr.loss(theta + e) - gr.loss(theta - e)) / (2 * step)
+
+        for k in range(lo, hi):
+            fd = (4 * central(k, h) - central(k, 2 * h)) / 3
+            per[k] = {"adjoint": float(grad[k]), "fd": float(fd)}
+            worst = max(worst, abs(fd - grad[k]) / gmax)
+            log(f"finite differences: angle {k} adjoint {grad[k]:+.6e} fd {fd:+.6e} (worst so far {worst:.2e})")
+        fd_check = {"angles": f"{lo}:{hi}", "h": h, "scheme": "Richardson (4 D(h) - D(2h)) / 3",
+                    "max_abs_err_over_grad_inf": worst, "seconds": time.perf_counter() - t0, "per_angle": per}
     cpu = None if args.no_cpu else grad_cpu_baseline(c, wl, theta, args.cpu_budget)
     out = {
         "metric": "reverse-mode gradients/sec of Re sum_j <Z_j> (64 angles, frozen decisions)",
@@ -367,7 +393,7 @@ def main_grad(args):
         "loss": loss, "replay_loss_equal": bool(loss_r == gr.loss0), "record_ms": 1e3 * t_rec,
         "replay_ms": 1e3 * t_replay, "gradient_over_replay": t / t_replay, "grad_inf_norm": float(np.max(np.abs(grad))),
         "arena_peak_gib": st["arena_peak_bytes"] / 2 ** 30, "tape_steps": int(st["tape_steps"]),
-        "roofline": None, "cpu_baseline": cpu,
+        "fd_check": fd_check, "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -652,6 +678,9 @@ def main():
     ap.add_argument("--score", choices=["fp32", "bf16", "replica"], default="fp32",
                     help="headline (fp32 or bf16) and mixed: the scoring of the timed path")
     ap.add_argument("--no-bf16", action="store_true", help="headline: skip the split-BF16 comparison run")
+    ap.add_argument("--fd-angles", default="",
+                    help="grad: check the adjoint against Richardson central differences on these angles "
+                         "(lo:hi or all; four replays of the full circuit per angle)")
     ap.add_argument("--no-exhaustive", action="store_true",
                     help="headline: skip the run with the exhaustive disentangler set")
     ap.add_argument("--no-replica", action="store_true",

@@ -74,8 +74,10 @@ enum {
  *   leaves (the truncation rule of the split applied to the singular values of the rotated
  *   two-site tensor) is below the identity's; among the candidates of the smallest bond
  *   dimension the smallest Renyi-2 entropy wins (lowest index within tie_tol).  Needs
- *   GCAMPS_SCORE_FP64; two-site matrices whose smaller side exceeds 32 or with more than 8192
- *   entries give EUNSUPPORTED. */
+ *   GCAMPS_SCORE_FP64.  Two-site matrices with smaller side <= 32 and at most 8192 entries are
+ *   ranked together by a one-sided Jacobi SVD per candidate; larger ones one candidate at a time
+ *   by the split's own factorisation (Gram eigen-decomposition, relative-accuracy second pass
+ *   where the rank floor decides), up to the factorisation's capacity. */
 enum { GCAMPS_CRITERION_RENYI2 = 0, GCAMPS_CRITERION_BOND_DIM = 1 };
 
 typedef struct gcamps_ctx gcamps_ctx;

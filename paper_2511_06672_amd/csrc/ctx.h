@@ -7,6 +7,8 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -141,6 +143,7 @@ struct gcamps_ctx {
   // basis sizes r, [2] their summed sides m, [3] attempts that fell back to the full basis
   double stats_red[4] = {0};
   int last_basis = 0;  // singular values resolved by the last factorisation (m, or r when reduced)
+  bool trace_fact = std::getenv("GCAMPS_TRACE_FACT") != nullptr;
   // gradient: recording and frozen replay (all null in ordinary use)
   std::vector<int32_t>* rank_rec = nullptr;          // kept rank of every factorisation
   std::vector<GateRec>* gate_rec = nullptr;          // Weyl string of every non-Clifford gate
@@ -209,6 +212,7 @@ struct gcamps_ctx {
     gram();
     // basis: nb columns of U (ld ldu); tail: weight outside the basis, always discarded
     int nb = m, ldu = m;
+    int sw_h = 0, sw_main = 0, sw_p2 = 0;  // sweeps of the eigen-decompositions (trace only)
     const double* tail = nullptr;
     const bool try_reduce = reduce && mode == 0 && cfg.cutoff > 0.0 && m > kSmallEig && !tape && !rank_rec &&
                             !rank_frz;
@@ -226,7 +230,7 @@ struct gcamps_ctx {
         // orthogonal to ~1e-14 of their norms even where lam is tiny (an absolute criterion
         // leaves them off by ~tr H / lam times that)
         launch_zgemm(stream, 1, 0, r, r, m, Z, m, Z, m, Utmp, r, one, 0, 1);
-        eig_hermitian(stream, Utmp, r, r, G, r, lam, 1, eig, st, nullptr);
+        eig_hermitian(stream, Utmp, r, r, G, r, lam, 1, eig, st, &sw_h);
         launch_zgemm(stream, 0, 0, m, r, r, Z, m, G, r, U, r, one, 0, 0);     // L Y
         launch_normalize_cols(stream, U, m, r, r);
         orthonormalize_cols(stream, U, Z, Utmp, m, r, 2);
@@ -242,7 +246,7 @@ struct gcamps_ctx {
         stats_red[3] += 1;
       }
     }
-    if (!reduced) eig_hermitian(stream, G, m, m, U, m, lam, 0, eig, st, nullptr);
+    if (!reduced) eig_hermitian(stream, G, m, m, U, m, lam, 0, eig, st, &sw_main);
     if (wide)
       launch_zgemm(stream, 1, 0, nb, q, m, U, ldu, M, q, B, q, one, 0, 0);
     else
@@ -251,7 +255,7 @@ struct gcamps_ctx {
       // Rayleigh-Ritz on the reduced basis: B B^H = U^H G U with the full Gram, so its
       // eigenvalues err by the square of the basis error where L L^H's err by tr S
       launch_zgemm(stream, 0, 1, nb, nb, kW, B, kW, B, kW, G, nb, one, 0, 1);
-      eig_hermitian(stream, G, nb, nb, Z, nb, lam, 0, eig, st, nullptr);
+      eig_hermitian(stream, G, nb, nb, Z, nb, lam, 0, eig, st, &sw_main);
       launch_zgemm(stream, 0, 0, m, nb, nb, U, ldu, Z, nb, Utmp, ldu, one, 0, 0);
       std::swap(U, Utmp);
       launch_zgemm(stream, 1, 0, nb, kW, nb, Z, nb, B, kW, B2, kW, one, 0, 0);
@@ -276,7 +280,7 @@ struct gcamps_ctx {
     if (pass2) {
       // accurate second pass on the nearly diagonal Gram of B (relative criterion)
       launch_zgemm(stream, 0, 1, nb, nb, kW, B, kW, B, kW, G, nb, one, 0, 1);
-      eig_hermitian(stream, G, nb, nb, Z, nb, lam, 1, eig, st, nullptr);
+      eig_hermitian(stream, G, nb, nb, Z, nb, lam, 1, eig, st, &sw_p2);
       launch_zgemm(stream, 0, 0, m, nb, nb, U, ldu, Z, nb, Utmp, ldu, one, 0, 0);
       std::swap(U, Utmp);
       launch_zgemm(stream, 1, 0, nb, kW, nb, Z, nb, B, kW, B2, kW, one, 0, 0);
@@ -296,6 +300,9 @@ struct gcamps_ctx {
       kstats[0] += 1;
       kstats[1] += 4.0 * (6.0 * pl * ql * ql + 20.0 * ql * ql * ql);
       kstats[2] += fms;
+      if (trace_fact)  // GCAMPS_TRACE_FACT: one line per factorisation on stderr
+        std::fprintf(stderr, "gcamps-fact m=%d k=%d mode=%d reduce=%d basis=%d kept=%d pass2=%d ms=%.3f sweeps=%d/%d/%d\n",
+                     m, kW, mode, reduced ? 1 : 0, nb, h.kept, pass2 ? 1 : 0, fms, sw_h, sw_main, sw_p2);
     }
     if (rank_rec) rank_rec->push_back(h.kept | (pass2 ? (1 << kPass2Bit) : 0));
     if (tape) {
@@ -321,6 +328,43 @@ struct gcamps_ctx {
                 Rout);
     last_basis = nb;
     return h;
+  }
+
+  // Kept rank of the split's truncation rule on M (p x q): the first pass and, where the rank
+  // floor matters, the relative-accuracy second pass of factorize(), without the factors, the
+  // counters or any record (the bond-dimension criterion on bonds above the batched kernel's
+  // size).
+  int split_rank(const z64* M, int p, int q) {
+    const bool wide = p <= q;
+    const int m = wide ? p : q, kW = wide ? q : p;
+    GC_CHECK((size_t)m <= lay.mcap && (size_t)m * kW <= lay.slot_elems, GCAMPS_ECAPACITY,
+             "factorisation exceeds workspace capacity");
+    const z64 one = {1.0, 0.0};
+    if (wide)
+      launch_zgemm(stream, 0, 1, m, m, q, M, q, M, q, G, m, one, 0, 1);
+    else
+      launch_zgemm(stream, 1, 0, m, m, p, M, q, M, q, G, m, one, 0, 1);
+    eig_hermitian(stream, G, m, m, U, m, lam, 0, eig, st, nullptr);
+    if (wide)
+      launch_zgemm(stream, 1, 0, m, q, m, U, m, M, q, B, q, one, 0, 0);
+    else
+      launch_zgemm(stream, 1, 1, m, p, m, U, m, M, q, B, p, one, 0, 0);
+    launch_rownorm2(stream, B, m, kW, kW, sig2);
+    launch_trunc(stream, sig2, m, cfg.cutoff, cfg.chi_max, 0, 0, perm, sig, st);
+    DevStatus h;
+    read_status(h);
+    GC_CHECK(m > kSmallEig || h.converged, GCAMPS_ENUMERIC, "eigensolver did not converge");
+    if (h.need_pass2) {
+      launch_zgemm(stream, 0, 1, m, m, kW, B, kW, B, kW, G, m, one, 0, 1);
+      eig_hermitian(stream, G, m, m, Z, m, lam, 1, eig, st, nullptr);
+      launch_zgemm(stream, 1, 0, m, kW, m, Z, m, B, kW, B2, kW, one, 0, 0);
+      launch_rownorm2(stream, B2, m, kW, kW, sig2);
+      launch_trunc(stream, sig2, m, cfg.cutoff, cfg.chi_max, 0, 0, perm, sig, st);
+      read_status(h);
+      GC_CHECK(m > kSmallEig || h.converged, GCAMPS_ENUMERIC, "eigensolver did not converge (second pass)");
+    }
+    GC_CHECK(std::isfinite(h.eps) && h.kept >= 1, GCAMPS_ENUMERIC, "factorisation produced non-finite values");
+    return h.kept;
   }
 
   // ---------------------------------------------------------------- centre moves (exact)
@@ -618,14 +662,6 @@ struct gcamps_ctx {
     int sweeps = 0, changed_total = 0;
     const int prec = cfg.score_prec;
     const bool frozen = choice_frz != nullptr;
-    if (cfg.criterion == GCAMPS_CRITERION_BOND_DIM && !frozen) {
-      // checked before any change: under this criterion no bond grows during the sweeps
-      for (int i = 0; i + 1 < n; ++i) {
-        const int mm = std::min(chi[i] * d, d * chi[i + 2]), kk = std::max(chi[i] * d, d * chi[i + 2]);
-        GC_CHECK(mm <= kRankMaxM && (size_t)(mm + (mm & 1)) * kk <= kRankMaxElems, GCAMPS_EUNSUPPORTED,
-                 "bond-dimension criterion: two-site matrix too large (smaller side <= 32, at most 8192 entries)");
-      }
-    }
     for (int sw = 0; sw < cfg.max_sweeps; ++sw) {
       ++sweeps;
       const bool ltr = (sw % 2 == 0);
@@ -661,7 +697,20 @@ struct gcamps_ctx {
                        lay.nbuf_bytes, gram_ev.data(), (int)gram_ev.size(), &gram_used, rtab);
           GC_HIP(hipEventRecord(ev1, stream));
           if (cfg.criterion == GCAMPS_CRITERION_BOND_DIM) {
-            launch_cand_rank(stream, d, cl, cr, theta, q64, ncand, cfg.cutoff, cfg.chi_max, wlist);
+            if (mm <= kRankMaxM && (size_t)(mm + (mm & 1)) * kk <= kRankMaxElems) {
+              launch_cand_rank(stream, d, cl, cr, theta, q64, ncand, cfg.cutoff, cfg.chi_max, wlist);
+            } else {
+              // larger bonds: every candidate's rotated tensor through the split's own
+              // factorisation (Lbuf holds Q_c Theta; the split of the bond comes later)
+              std::vector<int32_t> ranks(ncand);
+              for (int c = 0; c < ncand; ++c) {
+                launch_rotate_copy(stream, d, cl, cr, c, q64, theta, Lbuf);
+                ranks[c] = split_rank(Lbuf, cl * d, d * cr);
+              }
+              int32_t* hr = reinterpret_cast<int32_t*>(stage_begin());
+              std::memcpy(hr, ranks.data(), (size_t)ncand * sizeof(int32_t));
+              stage_upload(wlist, (size_t)ncand * sizeof(int32_t));
+            }
             launch_select_rank(stream, ncand, wlist, s2, cfg.tie_tol, st);
           } else if (prec == GCAMPS_SCORE_FP64) {
             launch_select(stream, ncand, s2, cfg.tie_tol, st);

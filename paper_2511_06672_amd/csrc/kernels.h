@@ -84,6 +84,9 @@ struct MpoTerms {
 };
 void launch_mpo_sum_site(hipStream_t s, int kind, int d, int J, int chil, int chir, const MpoTerms& terms,
                          const z64* in, z64* out);
+// out = Q_c Theta for the candidate c given by the host (a copy for c == 0).
+void launch_rotate_copy(hipStream_t s, int d, int chil, int chir, int c, const z64* qmats, const z64* theta,
+                        z64* out);
 // Theta <- Q_{cstar} Theta in place (no-op when cstar == 0).  Theta (chil, d, d, chir).
 void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* st, const z64* qmats,
                     z64* theta);

@@ -112,6 +112,26 @@ __global__ void k_apply_q(int d, int chil, int chir, const DevStatus* __restrict
   }
 }
 
+// out = Q_c Theta for an explicit candidate c (a copy when c == 0); Theta (chil, d, d, chir).
+__global__ void k_rotate_copy(int d, int chil, int chir, int c, const z64* __restrict__ qm,
+                              const z64* __restrict__ theta, z64* __restrict__ out) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)chil * chir) return;
+  const int a = (int)(idx / chir), b = (int)(idx % chir);
+  const int D2 = d * d;
+  const z64* q = qm + (size_t)c * D2 * D2;
+  z64 v[kMaxD * kMaxD];
+  for (int x = 0; x < D2; ++x) v[x] = theta[((size_t)a * D2 + x) * chir + b];
+  for (int y = 0; y < D2; ++y) {
+    z64 acc = {0.0, 0.0};
+    if (c == 0)
+      acc = v[y];
+    else
+      for (int x = 0; x < D2; ++x) acc = cadd(acc, cmul(q[y * D2 + x], v[x]));
+    out[((size_t)a * D2 + y) * chir + b] = acc;
+  }
+}
+
 // ===================================================================================== scoring
 // Element of M_c = reshape(Q_c Theta) at row (a, s1') and column (s2', b):
 //   M[(a s1'), (s2' b)] = sum_{s1 s2} Q[(s1' s2'), (s1 s2)] Theta[a, s1, s2, b]
@@ -1065,6 +1085,14 @@ void launch_mpo_sum_site(hipStream_t s, int kind, int d, int J, int chil, int ch
 void launch_apply_q(hipStream_t s, int d, int chil, int chir, const DevStatus* st, const z64* qmats, z64* theta) {
   size_t total = (size_t)chil * chir;
   hipLaunchKernelGGL(k_apply_q, dim3(blocks_for(total, 128)), dim3(128), 0, s, d, chil, chir, st, qmats, theta);
+  GC_LAUNCH_CHECK();
+}
+
+void launch_rotate_copy(hipStream_t s, int d, int chil, int chir, int c, const z64* qmats, const z64* theta,
+                        z64* out) {
+  const size_t total = (size_t)chil * chir;
+  hipLaunchKernelGGL(k_rotate_copy, dim3(blocks_for(total, 128)), dim3(128), 0, s, d, chil, chir, c, qmats, theta,
+                     out);
   GC_LAUNCH_CHECK();
 }
 

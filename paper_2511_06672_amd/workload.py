@@ -272,8 +272,10 @@ class Workload:
     candidate_set: str = "listed"
 
 
-def workload(name: str, n: int | None = None) -> Workload:
-    """Named workloads.  ``n`` overrides the chain length (keeping the recipe)."""
+def workload(name: str, n: int | None = None, layers: int | None = None) -> Workload:
+    """Named workloads.  ``n`` overrides the chain length (keeping the recipe); ``layers``
+    overrides the layer count of the paper workloads (default N, the onset of the transition;
+    the runs past it use up to 2N)."""
     if name == "exact_d3_n8":
         nn = 8 if n is None else n
         seed = 1000
@@ -299,7 +301,7 @@ def workload(name: str, n: int | None = None) -> Workload:
         dd = 3 if name == "paper_d3_n12" else 2
         nn = 12 if n is None else n
         seed = 6000 + dd
-        c = paper_circuit(dd, nn, nn, seed)
+        c = paper_circuit(dd, nn, nn if layers is None else layers, seed)
         return Workload(name, c, [], chi_max=min(dd ** (nn // 2), 1024), cutoff=0.0, candidate_set="exhaustive")
     if name == "mixed_d2_n64":
         # mixed run, qubit part: one T = diag(1, e^{i pi/4}) per layer, chi_max 1024, cutoff
