@@ -72,11 +72,13 @@ def main():
     gi = 0
     t_start = time.time()
     for L, layer in enumerate(c.layers):
+        # the covered prefix ends after a layer's non-Clifford gate, before the next layer's
+        # bricks, which is where the GPU test stops too (one T gate per layer here)
+        if gi >= max_gates or time.time() - t_start > budget:
+            return finish(rec, g, out_path)
         for b in layer.bricks:
             g.apply_clifford(b.site, b.word.gens, b.word.weyl)
         for ph in layer.phases:
-            if gi >= max_gates or time.time() - t_start > budget:
-                return finish(rec, g, out_path)
             t0 = time.time()
             g.apply_phase_rotation(ph.site, ph.phi)
             dt = time.time() - t0
