@@ -207,11 +207,11 @@ int32_t gcamps_score_bond(gcamps_ctx* ctx, int32_t bond, double* out, int64_t ca
  * to a caller's matrix so that it can be checked on its own.  m_host: p x q complex128,
  * row-major, interleaved (re, im), borrowed.  Requires min(p, q) and p * q within the ctx's
  * capacity (min(p, q) <= chi_max * max(d, max_gate_terms), p * q <= that times d times itself).
- * flags: 0, or GCAMPS_FACTORIZE_REDUCE for the path of the splits after a disentangler: with a
- * positive cutoff and min(p, q) > 32, a pivoted Cholesky factorisation of the Gram first finds a
- * basis of r columns holding all but at most min(1e-14, cutoff / (2 min(p, q))) of the weight
- * and the eigensolver runs on r x r; the remainder counts as discarded.  Without a useful
- * reduction (r > 3/4 min(p, q)) the full path runs.
+ * flags: 0, or GCAMPS_FACTORIZE_REDUCE for the path the truncating splits of the bottom loop
+ * take: with a positive cutoff and 320 < min(p, q) <= 1024, a pivoted Cholesky factorisation of
+ * the Gram first finds a basis of r columns holding all but at most
+ * min(1e-14, cutoff / (2 min(p, q))) of the weight and the eigensolver runs on r x r (followed by
+ * a Rayleigh-Ritz step on the full Gram); the remainder counts as discarded.
  * Outputs (host): sig_out[min(p, q)] the singular values in descending order (with
  * GCAMPS_FACTORIZE_REDUCE those of the reduced basis, zeros after them); *kept the rank
  * kept; *eps the discarded weight sum_{i >= kept} sigma_i^2 / sum_i sigma_i^2; if non-NULL,

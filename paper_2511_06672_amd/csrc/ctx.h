@@ -192,9 +192,10 @@ struct gcamps_ctx {
   // Split M (p x q, row-major) into L (p x k) R (k x q).  mode 0: truncation rule with
   // renormalisation; mode 1: exact (rank floor only).  left_ortho: L has orthonormal columns
   // (else R has orthonormal rows).  Returns the status block of the final pass.
-  // reduce: the split of a rotated two-site tensor, whose Gram is often of rank far below m; the
-  // eigensolver then runs on the r x r matrix of a pivoted Cholesky reduction (mode 0 with a
-  // positive cutoff, outside gradient recording and replay).
+  // reduce: a truncating split of the bottom loop (mode 0 with a positive cutoff, outside
+  // gradient recording and replay): the eigensolver runs on the r x r matrix of a pivoted
+  // Cholesky factorisation of the Gram, which drops what the cutoff could never keep (rotated
+  // two-site tensors often have rank far below m) and preconditions the Jacobi sweeps.
   DevStatus factorize(const z64* M, int p, int q, int mode, int left_ortho, z64* Lout, z64* Rout,
                       bool reduce = false) {
     const bool wide = p <= q;
@@ -214,18 +215,17 @@ struct gcamps_ctx {
     int nb = m, ldu = m;
     int sw_h = 0, sw_main = 0, sw_p2 = 0;  // sweeps of the eigen-decompositions (trace only)
     const double* tail = nullptr;
-    const bool try_reduce = reduce && mode == 0 && cfg.cutoff > 0.0 && m > kSmallEig && !tape && !rank_rec &&
-                            !rank_frz;
+    const bool try_reduce = reduce && mode == 0 && cfg.cutoff > 0.0 && m > kReduceMinM && m <= kReduceMaxM && !tape &&
+                            !rank_rec && !rank_frz;
     bool reduced = false;
     if (try_reduce) {
       // stop once the Schur complement's trace is below min(1e-14, cutoff / 2m) of the trace: then
       // its directions hold less than the cutoff even all together, and no eigenvalue moves by
       // more than the Gram's own rounding
       const double tol_rel = std::min(1e-14, cfg.cutoff / (2.0 * m));
-      const int rmax = (3 * m) / 4;
       PcState hs{};
-      const int r = pchol_reduce(stream, G, m, m, Z, m, tol_rel, rmax, sig, perm, pcst, &hs);
-      if (hs.done && r >= 1 && r <= rmax) {
+      const int r = pchol_reduce(stream, G, m, m, Z, m, tol_rel, m, sig, perm, pcst, &hs);
+      if (hs.done && r >= 1) {
         // H = L^H L = Y lam Y^H with relative accuracy, so that the columns of L Y are
         // orthogonal to ~1e-14 of their norms even where lam is tiny (an absolute criterion
         // leaves them off by ~tr H / lam times that)
@@ -534,7 +534,7 @@ struct gcamps_ctx {
       for (int i = l; i < r; ++i) move_right(i);
       for (int i = r; i > l; --i) {
         const int p = chi[i], q = d * chi[i + 1];
-        DevStatus h = factorize(site[i], p, q, 0, 0, Lbuf, Rbuf);
+        DevStatus h = factorize(site[i], p, q, 0, 0, Lbuf, Rbuf, true);
         const int k = h.kept;
         if (tape) tape_absorb(TAPE_ABSORB_L, i, site[i - 1], chi[i - 1] * d, p);
         std::swap(site[i], Rbuf);
@@ -744,14 +744,14 @@ struct gcamps_ctx {
         }
         DevStatus h;
         if (shortcut && ltr) {
-          h = factorize(site[i], cl * d, cm, 0, 1, Lbuf, Rbuf);
+          h = factorize(site[i], cl * d, cm, 0, 1, Lbuf, Rbuf, true);
           const int k = h.kept;
           if (tape) tape_absorb(TAPE_ABSORB_R, i, site[i + 1], cm, d * cr);
           launch_zgemm(stream, 0, 0, k, d * cr, cm, Rbuf, cm, site[i + 1], d * cr, spare, d * cr, z64{1.0, 0.0}, 0, 0);
           std::swap(site[i], Lbuf);
           std::swap(site[i + 1], spare);
         } else if (shortcut) {
-          h = factorize(site[i + 1], cm, d * cr, 0, 0, Lbuf, Rbuf);
+          h = factorize(site[i + 1], cm, d * cr, 0, 0, Lbuf, Rbuf, true);
           const int k = h.kept;
           if (tape) tape_absorb(TAPE_ABSORB_L, i + 1, site[i], cl * d, cm);
           launch_zgemm(stream, 0, 0, cl * d, k, cm, site[i], cm, Lbuf, k, spare, k, z64{1.0, 0.0}, 0, 0);

@@ -90,6 +90,12 @@ constexpr int kMaxN = 128;
 constexpr double kNearTieLowp = 1e-4;  // smallest re-score window with FP32 / split-BF16 scoring
 constexpr size_t kDenseMax = size_t(1) << 16;  // largest d^n of the dense (validation) state
 constexpr int kSmallEig = 32;   // largest m handled by the single-workgroup eigensolver
+// Truncating splits with kReduceMinM < m <= kReduceMaxM take the pivoted-Cholesky path: below,
+// its fixed costs (panel launches, two more eigensolves) outweigh what it saves (measured on the
+// headline workload: m = 81 0.95 against 0.62 ms, m = 243 3.1 against 2.1 ms); above, it is
+// untested against the plain path's accuracy.
+constexpr int kReduceMinM = 320;
+constexpr int kReduceMaxM = 1024;
 constexpr int kBlk = 16;        // block size of the multi-workgroup block Jacobi
 
 // ----------------------------------------------------------------- device status block

@@ -194,6 +194,12 @@ __global__ __launch_bounds__(kPcThreads) void k_pchol_panel(const z64* __restric
   }
 }
 
+// The factorisation ran through every row: nothing is left in the Schur complement.
+__global__ void k_pchol_finish(PcState* __restrict__ stt) {
+  stt->done = 1;
+  stt->tres = 0.0;
+}
+
 // Columns of X (m x r, ld ldx) scaled to unit norm; one workgroup per column.
 __global__ __launch_bounds__(256) void k_normalize_cols(z64* __restrict__ X, int m, int r, int ldx) {
   __shared__ double red[256];
@@ -259,6 +265,12 @@ int pchol_reduce(hipStream_t s, z64* G, int m, int ldg, z64* L, int ldl, double 
     GC_HIP(hipMemcpyAsync(host_state, stt, sizeof(PcState), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
     if (host_state->done || j0 >= m || host_state->r >= rmax) break;
+  }
+  if (!host_state->done && host_state->r >= m) {  // every row pivoted: the complement is empty
+    hipLaunchKernelGGL(k_pchol_finish, dim3(1), dim3(1), 0, s, stt);
+    GC_LAUNCH_CHECK();
+    host_state->done = 1;
+    host_state->tres = 0.0;
   }
   return host_state->r;
 }

@@ -23,10 +23,10 @@ The rank-reduced path (GCAMPS_FACTORIZE_REDUCE, used for the splits after a dise
 to the same bars: a pivoted Cholesky factorisation of the Gram stops once the remaining trace is
 below min(1e-14, cutoff / 2m) of the whole, so every singular value it leaves out has
 sigma^2 <= 5.6e-14 sigma_0^2 m here, inside the 1e-11 sigma_0^2 bar, and the remainder is counted
-as discarded weight (inside the 1e-12 absolute bar).  Cases: exact rank m/3 (the shape of a
+as discarded weight (inside the 1e-12 absolute bar); it applies for 320 < min(p, q) <= 1024.  Cases: exact rank m/3 (the shape of a
 rotated two-site tensor at chi = 256: 768 x 768, rank 256), rank plus noise below the bound, a
-decaying spectrum cut by the cutoff inside the reduced basis, and a full-rank matrix, where the
-reduction gives nothing and the full path must run.
+decaying spectrum cut by the cutoff inside the reduced basis, and a full-rank matrix, where every
+row is pivoted and the complement is empty.
 """
 import sys
 
@@ -116,7 +116,7 @@ def test_factorize_graded_spectrum_second_pass(g):
     assert abs(eps - np.sum(true[k:] ** 2) / np.sum(true ** 2)) <= 1e-15
 
 
-@pytest.mark.parametrize("p,q,r", [(768, 768, 256), (243, 729, 81), (729, 243, 81), (96, 96, 40)])
+@pytest.mark.parametrize("p,q,r", [(768, 768, 256), (729, 1458, 243), (1458, 729, 243), (400, 400, 150)])
 def test_factorize_reduced_exact_rank(g, p, q, r):
     say(f"factorize reduced, exact rank {r} in {p} x {q}")
     rng = np.random.default_rng(500 + p + q + r)
@@ -154,12 +154,21 @@ def test_factorize_reduced_noise_and_decaying_spectrum(g):
     assert st.kernel_stats()["reduced"] == 1
 
 
-def test_factorize_reduced_falls_back_on_full_rank(g):
-    say("factorize reduced on a full-rank 400 x 500 gaussian (falls back to the full basis)")
+def test_factorize_reduced_on_full_rank(g):
+    say("factorize through the Cholesky path on a full-rank 400 x 500 gaussian (every row pivoted)")
     rng = np.random.default_rng(502)
     st = state(g, CUT)
     k, _, _ = check(g, st, gauss(rng, 400, 500), CUT, factors=True, reduce=True)
     assert k == 400
+    ks = st.kernel_stats()
+    assert ks["reduced"] == 1 and ks["reduced_basis_frac"] == 1.0
+
+
+def test_factorize_small_sides_keep_the_plain_path(g):
+    say("factorize with the reduce flag at min side 200 (below the Cholesky path's range)")
+    rng = np.random.default_rng(503)
+    st = state(g, CUT)
+    check(g, st, gauss(rng, 200, 50) @ gauss(rng, 50, 300) / np.sqrt(50), CUT, factors=True, reduce=True)
     assert st.kernel_stats()["reduced"] == 0
 
 
