@@ -25,8 +25,9 @@ below min(1e-14, cutoff / 2m) of the whole, so every singular value it leaves ou
 sigma^2 <= 5.6e-14 sigma_0^2 m here, inside the 1e-11 sigma_0^2 bar, and the remainder is counted
 as discarded weight (inside the 1e-12 absolute bar); it applies for 320 < min(p, q) <= 1024.  Cases: exact rank m/3 (the shape of a
 rotated two-site tensor at chi = 256: 768 x 768, rank 256), rank plus noise below the bound, a
-decaying spectrum cut by the cutoff inside the reduced basis, and a full-rank matrix, where every
-row is pivoted and the complement is empty.
+decaying spectrum cut by the cutoff inside the reduced basis, a full-rank matrix, where every
+row is pivoted and the complement is empty, and with chi_max = 256: a cut set by the cap, a
+degenerate pair at the cap, and a plateau of weak values under the cutoff.
 """
 import sys
 
@@ -53,18 +54,18 @@ def g():
     return gcamps
 
 
-def state(g, cutoff):
-    return g.State(g.make_config(2, 2, CHI, cutoff, auto_disentangle=False, max_candidates=1))
+def state(g, cutoff, chi=CHI, d=2):
+    return g.State(g.make_config(d, 2, chi, cutoff, auto_disentangle=False, max_candidates=1))
 
 
 def gauss(rng, p, q):
     return (rng.standard_normal((p, q)) + 1j * rng.standard_normal((p, q))) / np.sqrt(2)
 
 
-def check(g, st, m, cutoff, factors, reduce=False, kept_tol=1e-12):
+def check(g, st, m, cutoff, factors, reduce=False, kept_tol=1e-12, chi=CHI):
     sig, k, eps, L, R = st.factorize(m, factors=factors, reduce=reduce)
     ref = np.linalg.svd(m, compute_uv=False)
-    kr, er, _ = rtrunc(ref, cutoff, CHI)
+    kr, er, _ = rtrunc(ref, cutoff, chi)
     s0 = ref[0]
     assert k == kr
     assert np.all(np.diff(sig) <= 0)
@@ -162,6 +163,49 @@ def test_factorize_reduced_on_full_rank(g):
     assert k == 400
     ks = st.kernel_stats()
     assert ks["reduced"] == 1 and ks["reduced_basis_frac"] == 1.0
+
+
+def spectrum_matrix(rng, n, true):
+    u, _, _ = svd(gauss(rng, n, n))
+    v, _, _ = svd(gauss(rng, n, n))
+    return (u * true) @ v.conj().T
+
+
+def test_factorize_reduced_cut_by_the_cap(g):
+    """chi_max = 256 on a 768 x 768 matrix with sigma_i = 10^(-0.012 i), the shape of a rotated
+    two-site tensor at chi = 256: the cap sets the cut (the tail after 256 values is 7e-7 of the
+    weight, far above the cutoff) inside a basis of ~600 columns."""
+    say("factorize reduced, cut by chi_max = 256: sigma_i = 10^(-0.012 i), 768 x 768")
+    rng = np.random.default_rng(504)
+    m = spectrum_matrix(rng, 768, 10.0 ** (-0.012 * np.arange(768)))
+    st = state(g, CUT, chi=256, d=3)
+    k, _, _ = check(g, st, m, CUT, factors=True, reduce=True, chi=256)
+    assert k == 256 and st.kernel_stats()["reduced"] == 1
+
+
+def test_factorize_reduced_degenerate_pair_at_the_cap(g):
+    """sigma_255 = sigma_256 exactly with chi_max 256: the degeneracy guard moves the cut to 255,
+    so that no multiplet is split."""
+    say("factorize reduced, degenerate pair at the cap: 768 x 768, chi_max 256")
+    rng = np.random.default_rng(506)
+    true = 10.0 ** (-0.012 * np.arange(768))
+    true[256] = true[255]
+    st = state(g, CUT, chi=256, d=3)
+    k, _, _ = check(g, st, spectrum_matrix(rng, 768, true), CUT, factors=True, reduce=True, chi=256)
+    assert k == 255
+
+
+def test_factorize_reduced_plateau_under_the_cutoff(g):
+    """100 values 10^(-0.02 i) above a plateau of 500 values sigma = 3e-7 (each ~8e-15 of the
+    weight, 4e-12 together): the cutoff discards the whole plateau, which the Cholesky
+    factorisation must still pivot almost entirely to reach its 1e-14 stop."""
+    say("factorize reduced, 100 values above a 500-value plateau, 600 x 600, chi_max 256")
+    rng = np.random.default_rng(505)
+    true = np.concatenate([10.0 ** (-0.02 * np.arange(100)), np.full(500, 3e-7)])
+    st = state(g, CUT, chi=256, d=3)
+    k, _, _ = check(g, st, spectrum_matrix(rng, 600, true), CUT, factors=True, reduce=True, chi=256)
+    ks = st.kernel_stats()
+    assert k == 100 and ks["reduced"] == 1 and ks["reduced_basis_frac"] > 256 / 600
 
 
 def test_factorize_small_sides_keep_the_plain_path(g):
