@@ -20,7 +20,8 @@ void launch_weyl_extract(hipStream_t s, int n, int d, const int* tx, const int* 
 
 // ------------------------------------------------------------------ dense linear algebra
 // C = alpha * op(A) op(B) (+ C if accumulate); row-major, complex128; op 0 = N, 1 = conj-transpose.
-// herm != 0: C is Hermitian (M == N): only the upper tiles are computed and mirrored.
+// herm != 0: C is Hermitian (M == N, op(B) = op(A)^H): only the upper triangle is computed and
+// mirrored.
 void launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, const z64* A, int lda,
                   const z64* B, int ldb, z64* C, int ldc, z64 alpha, int accumulate, int herm);
 // Hermitian eigen-decomposition by two-sided Jacobi.  G (m x m, ld ldg) is destroyed (holds

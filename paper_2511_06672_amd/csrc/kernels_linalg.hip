@@ -1,7 +1,7 @@
 // Dense FP64 complex linear algebra for the MPS factorisations (§2.4: truncation by SVD).
 //
-// * k_zgemm: C = alpha op(A) op(B) on 64x64 tiles with v_mfma_f64_16x16x4 (a complex product
-//   is four real MFMAs into a real and an imaginary accumulator).
+// * k_zgemm / k_zgemm_ks: C = alpha op(A) op(B) on 32x32 tiles with v_mfma_f64_16x16x4 (a
+//   complex product is four real MFMAs into a real and an imaginary accumulator).
 // * Hermitian eigen-decomposition by two-sided Jacobi rotations: a single-workgroup kernel that
 //   keeps the whole matrix in LDS (m <= kSmallEig) and a block-Jacobi scheme for larger m
 //   (pairs of 32-blocks solved in LDS, the rotations applied to the matrix and the eigenvector
@@ -19,108 +19,193 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 namespace {
 
 // ===================================================================================== GEMM
-constexpr int TM = 64, TK = 16, LPAD = 68;
+// Two forms, both on 32 x 32 output tiles (a 768 x 768 product has 576 of them, so that every
+// CU gets work where 64 x 64 tiles left 40% of the chip idle).  K advances in chunks of 16;
+// each chunk is fetched into registers while the previous one is multiplied, then stored into
+// the other LDS stage (one barrier per chunk).  A complex product is four real MFMAs into a real
+// and an imaginary accumulator.  Hermitian products (herm: M == N and op(B) = op(A)^H) compute
+// the upper triangle, diagonal included, and write its mirror.
+constexpr int GT = 32, GK = 16, GLD = GT + 4;
 
+// Output element (row, col) of a Hermitian or general product, with alpha and accumulate.
+__device__ __forceinline__ void gemm_store(z64* __restrict__ C, int ldc, int M, int N, int row, int col, double sr,
+                                           double si, z64 alpha, int accumulate, int herm) {
+  if (row >= M || col >= N || (herm && row > col)) return;
+  z64 v = {alpha.re * sr - alpha.im * si, alpha.re * si + alpha.im * sr};
+  if (accumulate) v = cadd(v, C[(size_t)row * ldc + col]);
+  C[(size_t)row * ldc + col] = v;
+  if (herm && row < col) C[(size_t)col * ldc + row] = cconj(v);
+}
+
+// Element e of a 32-row (or 32-column) operand tile times KC k values, as (row or column, k):
+// k fastest when LAYOUT is 0, the row or column fastest when it is 1.  Each operand takes the
+// order in which consecutive threads read consecutive addresses: A as is and B transposed are
+// contiguous along k (layout 0), A transposed and B as is along the row or column (layout 1).
+template <int LAYOUT, int KC>
+__device__ __forceinline__ void tile_elem(int e, int& rc, int& kk) {
+  if (LAYOUT == 0) {
+    rc = e / KC;
+    kk = e % KC;
+  } else {
+    rc = e % GT;
+    kk = e / GT;
+  }
+}
+template <int OP>
+__device__ __forceinline__ z64 load_a(const z64* __restrict__ A, int lda, int M, int K, int gr, int gk) {
+  z64 v = {0.0, 0.0};
+  if (gr < M && gk < K) {
+    if (OP == 0) {
+      v = A[(size_t)gr * lda + gk];
+    } else {
+      v = A[(size_t)gk * lda + gr];
+      v.im = -v.im;
+    }
+  }
+  return v;
+}
+template <int OP>
+__device__ __forceinline__ z64 load_b(const z64* __restrict__ B, int ldb, int N, int K, int gc, int gk) {
+  z64 v = {0.0, 0.0};
+  if (gc < N && gk < K) {
+    if (OP == 0) {
+      v = B[(size_t)gk * ldb + gc];
+    } else {
+      v = B[(size_t)gc * ldb + gk];
+      v.im = -v.im;
+    }
+  }
+  return v;
+}
+
+// Four waves, each a 16 x 16 quadrant of the tile, over every K chunk.
 template <int OPA, int OPB>
 __global__ __launch_bounds__(256) void k_zgemm(int M, int N, int K, const z64* __restrict__ A, int lda,
-                                               const z64* __restrict__ B, int ldb, z64* __restrict__ C,
-                                               int ldc, z64 alpha, int accumulate, int herm) {
-  const int tm = blockIdx.y, tn = blockIdx.x;
-  if (herm && tm > tn) return;
-  const int m0 = tm * TM, n0 = tn * TM;
-  __shared__ double As[2][TK][LPAD];
-  __shared__ double Bs[2][TK][LPAD];
+                                               const z64* __restrict__ B, int ldb, z64* __restrict__ C, int ldc,
+                                               z64 alpha, int accumulate, int herm) {
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  if (herm && m0 >= n0 + GT) return;  // entirely below the diagonal
+  __shared__ double As[2][2][GK][GLD];  // [stage][re, im][k][row]
+  __shared__ double Bs[2][2][GK][GLD];  // [stage][re, im][k][col]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  d4 accr[2][2], acci[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
-      accr[i][j] = (d4){0, 0, 0, 0};
-      acci[i][j] = (d4){0, 0, 0, 0};
-    }
-  for (int k0 = 0; k0 < K; k0 += TK) {
+  const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+  d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+  z64 ra[2], rb[2];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int e = t + 256 * i;
-      int row, kk;
-      if (OPA == 0) {
-        row = e >> 4;
-        kk = e & 15;
-      } else {
-        row = e & 63;
-        kk = e >> 6;
-      }
-      int gr = m0 + row, gk = k0 + kk;
-      z64 v = {0.0, 0.0};
-      if (gr < M && gk < K) {
-        if (OPA == 0)
-          v = A[(size_t)gr * lda + gk];
-        else {
-          v = A[(size_t)gk * lda + gr];
-          v.im = -v.im;
-        }
-      }
-      As[0][kk][row] = v.re;
-      As[1][kk][row] = v.im;
+    for (int i = 0; i < 2; ++i) {
+      int r, kk;
+      tile_elem<OPA, GK>(t + 256 * i, r, kk);
+      ra[i] = load_a<OPA>(A, lda, M, K, m0 + r, k0 + kk);
+      tile_elem<OPB == 0 ? 1 : 0, GK>(t + 256 * i, r, kk);
+      rb[i] = load_b<OPB>(B, ldb, N, K, n0 + r, k0 + kk);
     }
+  };
+  auto stash = [&](int s) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int e = t + 256 * i;
-      int col, kk;
-      if (OPB == 0) {
-        col = e & 63;
-        kk = e >> 6;
-      } else {
-        col = e >> 4;
-        kk = e & 15;
-      }
-      int gcn = n0 + col, gk = k0 + kk;
-      z64 v = {0.0, 0.0};
-      if (gcn < N && gk < K) {
-        if (OPB == 0)
-          v = B[(size_t)gk * ldb + gcn];
-        else {
-          v = B[(size_t)gcn * ldb + gk];
-          v.im = -v.im;
-        }
-      }
-      Bs[0][kk][col] = v.re;
-      Bs[1][kk][col] = v.im;
+    for (int i = 0; i < 2; ++i) {
+      int r, kk;
+      tile_elem<OPA, GK>(t + 256 * i, r, kk);
+      As[s][0][kk][r] = ra[i].re;
+      As[s][1][kk][r] = ra[i].im;
+      tile_elem<OPB == 0 ? 1 : 0, GK>(t + 256 * i, r, kk);
+      Bs[s][0][kk][r] = rb[i].re;
+      Bs[s][1][kk][r] = rb[i].im;
     }
-    __syncthreads();
+  };
+  const int nch = (K + GK - 1) / GK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int s = c & 1;
+    if (c + 1 < nch) fetch((c + 1) * GK);
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 4) {
+    for (int kk = 0; kk < GK; kk += 4) {
       const int ka = kk + (lane >> 4);
-      double ar[2], ai[2], br[2], bi[2];
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = As[0][ka][wr + i * 16 + (lane & 15)];
-        ai[i] = As[1][ka][wr + i * 16 + (lane & 15)];
-        br[i] = Bs[0][ka][wc + i * 16 + (lane & 15)];
-        bi[i] = Bs[1][ka][wc + i * 16 + (lane & 15)];
-      }
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {
-          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
-          accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], accr[i][j], 0, 0, 0);
-          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acci[i][j], 0, 0, 0);
-          acci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acci[i][j], 0, 0, 0);
-        }
+      const double ar = As[s][0][ka][wr + (lane & 15)], ai = As[s][1][ka][wr + (lane & 15)];
+      const double br = Bs[s][0][ka][wc + (lane & 15)], bi = Bs[s][1][ka][wc + (lane & 15)];
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, acci, 0, 0, 0);
     }
+    if (c + 1 < nch) stash(s ^ 1);
     __syncthreads();
   }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      for (int q = 0; q < 4; ++q) {
-        int row = m0 + wr + i * 16 + mfma_row_f64(lane, q);
-        int col = n0 + wc + j * 16 + (lane & 15);
-        if (row < M && col < N) {
-          z64 v = {alpha.re * accr[i][j][q] - alpha.im * acci[i][j][q],
-                   alpha.re * acci[i][j][q] + alpha.im * accr[i][j][q]};
-          if (accumulate) v = cadd(v, C[(size_t)row * ldc + col]);
-          C[(size_t)row * ldc + col] = v;
-          if (herm && tm < tn) C[(size_t)col * ldc + row] = cconj(v);
-        }
-      }
+  for (int q = 0; q < 4; ++q)
+    gemm_store(C, ldc, M, N, m0 + wr + mfma_row_f64(lane, q), n0 + wc + (lane & 15), accr[q], acci[q], alpha,
+               accumulate, herm);
+}
+
+// Eight waves for products with few tiles: wave group g (waves 4g..4g+3, one 16 x 16 quadrant
+// each) takes chunk 2p + g of every chunk pair p, and group 1 hands its sums to group 0 through
+// LDS at the end (two partial sums per element, added in a fixed order).
+template <int OPA, int OPB>
+__global__ __launch_bounds__(512) void k_zgemm_ks(int M, int N, int K, const z64* __restrict__ A, int lda,
+                                                  const z64* __restrict__ B, int ldb, z64* __restrict__ C, int ldc,
+                                                  z64 alpha, int accumulate, int herm) {
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  if (herm && m0 >= n0 + GT) return;
+  __shared__ double As[2][2][2][GK][GLD];  // [stage][group][re, im][k][row]
+  __shared__ double Bs[2][2][2][GK][GLD];
+  __shared__ double Xr[4][4][64], Xi[4][4][64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, grp = w >> 2, wl = w & 3;
+  const int wr = (wl >> 1) * 16, wc = (wl & 1) * 16;
+  d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+  z64 ra[2], rb[2];
+  auto fetch = [&](int k0) {  // a chunk pair: 32 rows x 32 k values of each operand
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int r, kk;
+      tile_elem<OPA, 2 * GK>(t + 512 * i, r, kk);
+      ra[i] = load_a<OPA>(A, lda, M, K, m0 + r, k0 + kk);
+      tile_elem<OPB == 0 ? 1 : 0, 2 * GK>(t + 512 * i, r, kk);
+      rb[i] = load_b<OPB>(B, ldb, N, K, n0 + r, k0 + kk);
+    }
+  };
+  auto stash = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int r, kk;
+      tile_elem<OPA, 2 * GK>(t + 512 * i, r, kk);
+      As[s][kk / GK][0][kk % GK][r] = ra[i].re;
+      As[s][kk / GK][1][kk % GK][r] = ra[i].im;
+      tile_elem<OPB == 0 ? 1 : 0, 2 * GK>(t + 512 * i, r, kk);
+      Bs[s][kk / GK][0][kk % GK][r] = rb[i].re;
+      Bs[s][kk / GK][1][kk % GK][r] = rb[i].im;
+    }
+  };
+  const int npair = (K + 2 * GK - 1) / (2 * GK);
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int c = 0; c < npair; ++c) {
+    const int s = c & 1;
+    if (c + 1 < npair) fetch((c + 1) * 2 * GK);
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      const int ka = kk + (lane >> 4);
+      const double ar = As[s][grp][0][ka][wr + (lane & 15)], ai = As[s][grp][1][ka][wr + (lane & 15)];
+      const double br = Bs[s][grp][0][ka][wc + (lane & 15)], bi = Bs[s][grp][1][ka][wc + (lane & 15)];
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, acci, 0, 0, 0);
+    }
+    if (c + 1 < npair) stash(s ^ 1);
+    __syncthreads();
+  }
+  if (grp == 1)
+    for (int q = 0; q < 4; ++q) {
+      Xr[wl][q][lane] = accr[q];
+      Xi[wl][q][lane] = acci[q];
+    }
+  __syncthreads();
+  if (grp == 0)
+    for (int q = 0; q < 4; ++q)
+      gemm_store(C, ldc, M, N, m0 + wr + mfma_row_f64(lane, q), n0 + wc + (lane & 15), accr[q] + Xr[wl][q][lane],
+                 acci[q] + Xi[wl][q][lane], alpha, accumulate, herm);
 }
 
 // ===================================================================================== Jacobi
@@ -860,19 +945,30 @@ inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / 
 void launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, const z64* A, int lda, const z64* B,
                   int ldb, z64* C, int ldc, z64 alpha, int accumulate, int herm) {
   if (M <= 0 || N <= 0) return;
-  dim3 grid((N + TM - 1) / TM, (M + TM - 1) / TM);
+  const dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+  // Below 256 tiles (Hermitian: counting the upper ones) the K-split form with two waves per
+  // SIMD is faster (768 x 256 x 768: 39 against 54 us), above it the four-wave form (768^3:
+  // 108 against 112 us; both against 226 us on 64 x 64 single-stage tiles).
+  const long tiles = herm ? (long)grid.x * (grid.x + 1) / 2 : (long)grid.x * grid.y;
+  const bool ks = tiles < 256;
+#define GC_ZGEMM(OA, OB)                                                                                         \
+  do {                                                                                                           \
+    if (ks)                                                                                                      \
+      hipLaunchKernelGGL((k_zgemm_ks<OA, OB>), grid, dim3(512), 0, s, M, N, K, A, lda, B, ldb, C, ldc, alpha,    \
+                         accumulate, herm);                                                                      \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_zgemm<OA, OB>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, alpha,       \
+                         accumulate, herm);                                                                      \
+  } while (0)
   if (opa == 0 && opb == 0)
-    hipLaunchKernelGGL((k_zgemm<0, 0>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, alpha, accumulate,
-                       herm);
+    GC_ZGEMM(0, 0);
   else if (opa == 0 && opb == 1)
-    hipLaunchKernelGGL((k_zgemm<0, 1>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, alpha, accumulate,
-                       herm);
+    GC_ZGEMM(0, 1);
   else if (opa == 1 && opb == 0)
-    hipLaunchKernelGGL((k_zgemm<1, 0>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, alpha, accumulate,
-                       herm);
+    GC_ZGEMM(1, 0);
   else
-    hipLaunchKernelGGL((k_zgemm<1, 1>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, alpha, accumulate,
-                       herm);
+    GC_ZGEMM(1, 1);
+#undef GC_ZGEMM
   GC_LAUNCH_CHECK();
 }
 
