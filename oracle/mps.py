@@ -67,6 +67,30 @@ def rtrunc(sigma: np.ndarray, cutoff: float, chi_max: int,
     return k, float(tail[k]), flagged
 
 
+def bond_renyi2(tensors: List[np.ndarray]) -> List[float]:
+    """Renyi-2 entropy S2 = -ln(sum_k lambda_k^2) across every bond of the chain, with lambda_k the
+    squared Schmidt coefficients of the cut normalised to sum 1 (Sec. 3: the entanglement
+    measure the disentangler minimises, here evaluated on the committed state).  Works in any
+    gauge: QR steps make every site left-orthonormal, then SVDs from the right read off each
+    bond's Schmidt coefficients (the right part being right-orthonormal by then)."""
+    ts = [np.array(t, dtype=np.complex128) for t in tensors]
+    n = len(ts)
+    for i in range(n - 1):
+        cl, d, cr = ts[i].shape
+        q, r = np.linalg.qr(ts[i].reshape(cl * d, cr))
+        ts[i] = q.reshape(cl, d, q.shape[1])
+        ts[i + 1] = np.einsum("ab,bsc->asc", r, ts[i + 1])
+    out = [0.0] * (n - 1)
+    for i in range(n - 1, 0, -1):
+        cl, d, cr = ts[i].shape
+        u, s, vh = np.linalg.svd(ts[i].reshape(cl, d * cr), full_matrices=False)
+        lam = s ** 2 / np.sum(s ** 2)
+        out[i - 1] = float(-np.log(np.sum(lam ** 2)))
+        ts[i] = vh.reshape(len(s), d, cr)
+        ts[i - 1] = np.einsum("asb,bc->asc", ts[i - 1], u * s[None, :])
+    return out
+
+
 class MPS:
     def __init__(self, d: int, tensors: List[np.ndarray], centre: int = 0):
         self.d = d

@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 from oracle.gcamps import Config, Gcamps  # noqa: E402
+from oracle.mps import bond_renyi2  # noqa: E402
 from paper_2511_06672_amd.workload import workload  # noqa: E402
 
 
@@ -71,6 +72,7 @@ def main():
         zs.append([v.real, v.imag])
     rec["final_z_expectations"] = zs
     rec["final_tableau"] = g.tab.export().tolist()
+    rec["final_bond_renyi2"] = bond_renyi2(g.mps.tensors)
     rec["final_after_gates"] = rec["gates_done"]
     with open(out_path + ".tmp", "w") as f:
         json.dump(rec, f)

@@ -23,6 +23,7 @@ import numpy as np  # noqa: E402
 
 from oracle.disentanglers import all_cliffords  # noqa: E402
 from oracle.gcamps import Config, Gcamps  # noqa: E402
+from oracle.mps import bond_renyi2  # noqa: E402
 from paper_2511_06672_amd.workload import Word, workload  # noqa: E402
 
 
@@ -48,6 +49,7 @@ def finish(rec, g, out_path):
         zs.append([v.real, v.imag])
     rec["final_z_expectations"] = zs
     rec["final_tableau"] = g.tab.export().tolist()
+    rec["final_bond_renyi2"] = bond_renyi2(g.mps.tensors)
     rec["final_after_gates"] = rec.get("gates_done", 0)
     with open(out_path + ".tmp", "w") as f:
         json.dump(rec, f)

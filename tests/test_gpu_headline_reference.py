@@ -19,11 +19,14 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "headline_d3_n32_oracle.json")
 F_TOL = 1e-9
 Z_TOL = 1e-8     # final <Z_j>: every scoring mode commits with the same FP64 factorisations
+S2_TOL = 1e-8    # final bond S2 (values up to ln chi_max; the states agree to ~1e-12)
 
 
 def check_final_state(st, ref, n, tol):
-    """<Z_j> for every site and the whole tableau after the reference's last gate (§3
-    observables: C^dagger Z_j C evaluated on the MPS by transfer matrices)."""
+    """<Z_j> for every site, the whole tableau and the Renyi-2 entropy across every bond of the
+    MPS after the reference's last gate (§3 observables: C^dagger Z_j C evaluated on the MPS by
+    transfer matrices; the bond entropies, gauge-invariant, pin the committed state where the
+    <Z_j> of a highly entangled state all sit near zero)."""
     if "final_z_expectations" not in ref:  # written by the reference scripts after the last gate
         print("[gpu-case] reference holds no final state", flush=True)
         return
@@ -34,6 +37,12 @@ def check_final_state(st, ref, n, tol):
     print(f"[gpu-case] final <Z_j>: largest difference {err:.2e}", flush=True)
     assert err <= tol, f"final <Z_j> differ by {err:.3e}"
     assert np.array_equal(st.tableau(), np.array(ref["final_tableau"])), "final tableau differs"
+    if "final_bond_renyi2" in ref:  # S2 across every bond of the committed MPS, any gauge
+        from oracle.mps import bond_renyi2
+        s2 = np.array(bond_renyi2([st.site(i) for i in range(n)]))
+        err = float(np.max(np.abs(s2 - np.array(ref["final_bond_renyi2"]))))
+        print(f"[gpu-case] final bond S2: largest difference {err:.2e} (largest S2 {s2.max():.3f})", flush=True)
+        assert err <= S2_TOL, f"final bond S2 differ by {err:.3e}"
 
 
 def digest(tab):

@@ -69,6 +69,38 @@ def test_svd_sweep_gives_schmidt_values():
         assert m.bond_dims()[cut - 1] == int(np.sum(sv > 1e-13 * sv[0]))
 
 
+def test_bond_renyi2_against_dense_cuts():
+    """bond_renyi2 on an MPS in a random gauge (an invertible matrix and its inverse inserted on
+    every bond) equals -ln sum p^2 from the singular values of the dense vector reshaped across
+    each cut; a product state gives 0 everywhere and a maximally entangled pair ln d."""
+    from oracle.mps import bond_renyi2
+    rng = np.random.default_rng(11)
+    d = 3
+    m = random_mps(d, [3, 5, 4], 2)
+    v0 = m.to_dense()
+    ts = [t.copy() for t in m.tensors]
+    for i in range(len(ts) - 1):
+        k = ts[i].shape[2]
+        x = rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k)) + 3 * np.eye(k)
+        ts[i] = np.einsum("asb,bc->asc", ts[i], x)
+        ts[i + 1] = np.einsum("cb,bsa->csa", np.linalg.inv(x), ts[i + 1])
+    got = bond_renyi2(ts)
+    for cut in range(1, 4):
+        sv = np.linalg.svd(v0.reshape(d ** cut, -1), compute_uv=False)
+        p = sv ** 2 / np.sum(sv ** 2)
+        assert abs(got[cut - 1] + np.log(np.sum(p ** 2))) < 1e-12
+    prod = [np.ones((1, d, 1), np.complex128) / np.sqrt(d) for _ in range(4)]
+    assert np.allclose(bond_renyi2(prod), 0.0, atol=1e-14)
+    # |00> + |11> + |22> on sites (1, 2) of a 4-site chain
+    a = np.zeros((1, d, d), np.complex128)
+    b = np.zeros((d, d, 1), np.complex128)
+    for s in range(d):
+        a[0, s, s] = 1 / np.sqrt(d)
+        b[s, s, 0] = 1.0
+    pair = [np.eye(1, d).reshape(1, d, 1).astype(np.complex128), a, b, np.eye(1, d).reshape(1, d, 1).astype(np.complex128)]
+    assert np.allclose(bond_renyi2(pair), [0.0, np.log(d), 0.0], atol=1e-13)
+
+
 def test_diagonal_coefficients_closed_form():
     for d in (2, 3, 5):
         rng = np.random.default_rng(d)
