@@ -183,7 +183,7 @@ def cpu_baseline(wl, budget_s, gate_clock=None):
         rec = json.load(open(os.path.join(ROOT, "tests", "golden", "headline_d3_n32_oracle.json")))
         if rec.get("gates_done") == c.n_phase_gates and c.n == rec.get("n"):
             ref = {"seconds": rec["cpu_seconds_total"], "value": c.n_phase_gates / rec["cpu_seconds_total"],
-                   "where": "the build host (4 BLAS threads), when the stored oracle reference was written"}
+                   "where": "the build host, when the stored oracle reference was written"}
     except (OSError, ValueError, KeyError):
         pass
     return {"value": done / dt, "unit": "non-Clifford gates/s", "cores": int(threads), "kind": "oracle",
