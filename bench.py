@@ -668,7 +668,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--workload", choices=["headline", "batch", "grad", "paper", "gates", "mixed", "copy"], default="headline")
     ap.add_argument("--batch-count", type=int, default=256)
-    ap.add_argument("--lanes", type=int, default=8,
+    ap.add_argument("--lanes", type=int, default=12,
                     help="batch: concurrent lanes (host threads with their own streams)")
     ap.add_argument("--batch-chunk", type=int, default=0,
                     help="batch: run the circuits in chunks of this many (progress lines; 0 = all at once)")
