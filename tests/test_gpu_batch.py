@@ -110,18 +110,18 @@ def test_batch_without_candidates_only_compresses():
 
 
 def test_many_lanes_on_the_batch_workload():
-    """32 circuits of the batch workload on 8 concurrent lanes: every circuit completes, and two
+    """32 circuits of the batch workload on 12 concurrent lanes: every circuit completes, and two
     of them equal their single-state runs bit for bit.  (Concurrent lanes slow some waves of a
     workgroup relative to others; the single-workgroup eigensolver once read its convergence
     flag after the next sweep had reset it, which only showed up under such load.)"""
     from paper_2511_06672_amd import gcamps as g
     from paper_2511_06672_amd.workload import batch_workload
-    print("[gpu-case] batch workload, 32 circuits on 8 lanes", flush=True)
+    print("[gpu-case] batch workload, 32 circuits on 12 lanes", flush=True)
     bw = batch_workload(count=32)
     cfgs = [g.make_config(3, c.n, bw.chi_max, bw.cutoff, score_prec=g.SCORE_FP32, near_tie=1e-4,
                           max_sweeps=bw.max_sweeps, max_candidates=len(bw.candidates)) for c in bw.circuits]
     cs = g.CandSet(3, bw.candidates)
-    res, stats = g.batch_run(bw.circuits, cfgs, cs, lanes=8)
+    res, stats = g.batch_run(bw.circuits, cfgs, cs, lanes=12)
     assert all(r["status"] == 0 for r in res) and stats["circuits"] == 32
     for i in (0, 19):
         st, _ = single_state(g, bw.circuits[i], cfgs[i], cs)
@@ -130,7 +130,7 @@ def test_many_lanes_on_the_batch_workload():
 
 
 def test_batch_workload_sample_against_oracle_reference():
-    """The first 32 circuits of the batch workload in one batch on 8 lanes (the benchmark's
+    """The first 32 circuits of the batch workload in one batch on 12 lanes (the benchmark's
     configuration: FP32 scoring with the FP64 near-tie window); eight of them, from product-like
     to one that reaches chi_max = 128 with truncation, against the oracle's references
     (tests/golden/batch_d3_sample_oracle.json, written by make_batch_reference.py from oracle/
@@ -142,10 +142,10 @@ def test_batch_workload_sample_against_oracle_reference():
     ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch_d3_sample_oracle.json")))
     bw = batch_workload(count=32)
     assert ref["chi_max"] == bw.chi_max and ref["candidates"] == len(bw.candidates)
-    print("[gpu-case] batch workload, 32 circuits on 8 lanes, oracle sample", flush=True)
+    print("[gpu-case] batch workload, 32 circuits on 12 lanes, oracle sample", flush=True)
     cfgs = [g.make_config(3, c.n, bw.chi_max, bw.cutoff, score_prec=g.SCORE_FP32, near_tie=1e-4,
                           max_sweeps=bw.max_sweeps, max_candidates=len(bw.candidates)) for c in bw.circuits]
-    res, _ = g.batch_run(bw.circuits, cfgs, g.CandSet(3, bw.candidates), lanes=8)
+    res, _ = g.batch_run(bw.circuits, cfgs, g.CandSet(3, bw.candidates), lanes=12)
     for r in ref["circuits"]:
         i = r["index"]
         mine = res[i]

@@ -21,7 +21,8 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-F_TOL = 1e-9
+F_TOL = 1e-10    # relative F_est; each split's discarded weight errs by ~(values discarded) x 2^-53
+                 # of the trace: ~3e-11 over 400 splits at m = 768 (measured 4e-13 here, 2e-11 at most)
 Z_TOL = 1e-8     # final <Z_j>: every scoring mode commits with the same FP64 factorisations
 
 
@@ -67,6 +68,7 @@ def test_general_workload_against_oracle_reference(name, prec):
                                max_gate_terms=c.d ** (2 * k)))
     st.set_candset(g.CandSet(c.d, cands))
     gi, prev = 0, 0
+    fgap = 0.0
     for layer in c.layers:
         if layer.bricks:
             st.apply_clifford_layer([b.site for b in layer.bricks], [b.word for b in layer.bricks])
@@ -79,7 +81,9 @@ def test_general_workload_against_oracle_reference(name, prec):
             assert [list(map(int, x[1:])) for x in mine] == r["choices"], f"choices differ at gate {gi}"
             assert st.bond_dims() == r["bond_dims"], f"bond dims differ at gate {gi}"
             assert digest(st.tableau()) == r["tableau_sha256"], f"tableau differs at gate {gi}"
+            fgap = max(fgap, abs(st.fidelity() - r["f_est"]) / r["f_est"])
             assert abs(st.fidelity() - r["f_est"]) <= F_TOL * r["f_est"], f"fidelity differs at gate {gi}"
             gi += 1
     assert gi == ngates
+    print(f"[gpu-case] matched {gi} gates, largest relative F_est gap {fgap:.2e}", flush=True)
     check_final_state(st, ref, c.n, Z_TOL)
