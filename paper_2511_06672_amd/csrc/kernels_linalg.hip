@@ -4,8 +4,8 @@
 //   complex product is four real MFMAs into a real and an imaginary accumulator).
 // * Hermitian eigen-decomposition by two-sided Jacobi rotations: a single-workgroup kernel that
 //   keeps the whole matrix in LDS (m <= kSmallEig) and a block-Jacobi scheme for larger m
-//   (pairs of 32-blocks solved in LDS, the rotations applied to the matrix and the eigenvector
-//   accumulator as 64x64 MFMA tile products).
+//   (pairs of 16-blocks solved as 32x32 sub-problems in LDS, the rotations applied to the matrix
+//   and the eigenvector accumulator as 32x32 MFMA tile products).
 // * k_trunc: descending sort of squared singular values and the truncation rule.
 // * k_emit: writes the two factors of a split in the requested orientation.
 #include <cfloat>
@@ -579,102 +579,6 @@ __device__ __forceinline__ int pair_index(int P, int i, int step, int nb) {
   return i < BJ ? I * BJ + i : J * BJ + (i - BJ);
 }
 
-// Kernel B: tiles (P, Q), P <= Q, of G <- V_P^H G V_Q (the (Q, P) tile is written as the conjugate
-// transpose) and row tiles of U <- U V_Q (32x32 tiles); tile index blockIdx.x + tile0, the G
-// tiles first.
-__global__ __launch_bounds__(256) void k_jblock_apply(z64* __restrict__ Gp, z64* __restrict__ Up, int mp, int nb,
-                                                      int step, const z64* __restrict__ V,
-                                                      const int* __restrict__ pair_flag, int tile0) {
-  extern __shared__ double smem[];
-  double* a_re = smem;
-  double* a_im = a_re + BJ2 * SLD;
-  double* b_re = a_im + BJ2 * SLD;
-  double* b_im = b_re + BJ2 * SLD;
-  const int half = nb / 2;
-  const int ngt = half * (half + 1) / 2;  // G tiles (P, Q) with P <= Q; (Q, P) is the mirror
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int lane = t & 63, w = t >> 6;
-  const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
-  int tile = blockIdx.x + tile0;
-  d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-  if (tile < ngt) {
-    int P = 0, rem = tile;
-    while (rem >= half - P) {
-      rem -= half - P;
-      ++P;
-    }
-    const int Q = P + rem;
-    const int fP = pair_flag[P], fQ = pair_flag[Q];
-    if (!fP && !fQ) return;
-    const z64* VP = V + (size_t)P * BJ2 * BJ2;
-    const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
-    // V_P is needed after the first product: fetch it into registers now
-    constexpr int PER = BJ2 * BJ2 / 256;
-    z64 vp[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int idx = t + 256 * u;
-      const int r = idx / BJ2, c = idx % BJ2;
-      vp[u] = fP ? VP[idx] : ((r == c) ? z64{1.0, 0.0} : z64{0.0, 0.0});
-    }
-    // a[kk][row] = T[row][kk] = G[rows(P)[row], cols(Q)[kk]];  b = V_Q (or identity)
-    for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
-      const int row = idx / BJ2, kk = idx % BJ2;
-      const z64 v = Gp[(size_t)pair_index(P, row, step, nb) * mp + pair_index(Q, kk, step, nb)];
-      a_re[kk * SLD + row] = v.re;
-      a_im[kk * SLD + row] = v.im;
-      const z64 q = fQ ? VQ[idx] : ((row == kk) ? z64{1.0, 0.0} : z64{0.0, 0.0});
-      b_re[row * SLD + kk] = q.re;
-      b_im[row * SLD + kk] = q.im;
-    }
-    __syncthreads();
-    mm32(a_re, a_im, b_re, b_im, false, accr, acci);  // X = T V_Q
-    __syncthreads();
-    for (int q = 0; q < 4; ++q) {
-      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
-      b_re[row * SLD + col] = accr[q];
-      b_im[row * SLD + col] = acci[q];
-      accr[q] = 0.0;
-      acci[q] = 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int idx = t + 256 * u;
-      const int r = idx / BJ2, c = idx % BJ2;
-      a_re[r * SLD + c] = vp[u].re;
-      a_im[r * SLD + c] = vp[u].im;
-    }
-    __syncthreads();
-    mm32(a_re, a_im, b_re, b_im, true, accr, acci);  // Y = V_P^H X
-    for (int q = 0; q < 4; ++q) {
-      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
-      const int gr = pair_index(P, row, step, nb), gc = pair_index(Q, col, step, nb);
-      Gp[(size_t)gr * mp + gc] = z64{accr[q], acci[q]};
-      if (P != Q) Gp[(size_t)gc * mp + gr] = z64{accr[q], -acci[q]};
-    }
-  } else {
-    tile -= ngt;
-    const int R = tile / half, Q = tile % half;
-    if (!pair_flag[Q]) return;
-    const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
-    for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
-      const int row = idx / BJ2, kk = idx % BJ2;
-      const z64 v = Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, kk, step, nb)];
-      a_re[kk * SLD + row] = v.re;
-      a_im[kk * SLD + row] = v.im;
-      const z64 q = VQ[idx];
-      b_re[row * SLD + kk] = q.re;
-      b_im[row * SLD + kk] = q.im;
-    }
-    __syncthreads();
-    mm32(a_re, a_im, b_re, b_im, false, accr, acci);
-    for (int q = 0; q < 4; ++q) {
-      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
-      Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, col, step, nb)] = z64{accr[q], acci[q]};
-    }
-  }
-}
-
 // One 32x32 row tile (R, Q) of U <- U V_Q with 512 threads: all threads stage the operands, the
 // first four waves multiply (planes re/im in a_*/b_*, 32 x SLD each).
 __device__ void u_tile(z64* __restrict__ Up, int mp, int nb, int step, const z64* __restrict__ V,
@@ -705,6 +609,88 @@ __device__ void u_tile(z64* __restrict__ Up, int mp, int nb, int step, const z64
       Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, col, step, nb)] = z64{accr[q], acci[q]};
     }
   }
+}
+
+// One 32x32 tile (P, Q), P <= Q, of G <- V_P^H G V_Q with 512 threads (all stage the
+// operands, the first four waves multiply); the (Q, P) tile is written as the conjugate
+// transpose.  A pair that did not rotate contributes the identity; a tile whose two pairs both
+// did not rotate is left as it is.
+__device__ void g_tile(z64* __restrict__ Gp, int mp, int nb, int step, const z64* __restrict__ V,
+                       const int* __restrict__ pair_flag, int tile, double* __restrict__ a_re,
+                       double* __restrict__ a_im, double* __restrict__ b_re, double* __restrict__ b_im) {
+  const int half = nb / 2;
+  int P = 0, rem = tile;
+  while (rem >= half - P) {
+    rem -= half - P;
+    ++P;
+  }
+  const int Q = P + rem;
+  const int fP = pair_flag[P], fQ = pair_flag[Q];
+  if (!fP && !fQ) return;  // uniform over the block
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+  const z64* VP = V + (size_t)P * BJ2 * BJ2;
+  const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
+  // V_P is needed after the first product: fetch it into registers now
+  z64 vp[BJ2 * BJ2 / kSolveThreads];
+#pragma unroll
+  for (int u = 0; u < BJ2 * BJ2 / kSolveThreads; ++u) {
+    const int idx = t + kSolveThreads * u;
+    const int r = idx / BJ2, c = idx % BJ2;
+    vp[u] = fP ? VP[idx] : ((r == c) ? z64{1.0, 0.0} : z64{0.0, 0.0});
+  }
+  // a[kk][row] = T[row][kk] = G[rows(P)[row], cols(Q)[kk]];  b = V_Q (or the identity)
+  for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+    const int row = idx / BJ2, kk = idx % BJ2;
+    const z64 v = Gp[(size_t)pair_index(P, row, step, nb) * mp + pair_index(Q, kk, step, nb)];
+    a_re[kk * SLD + row] = v.re;
+    a_im[kk * SLD + row] = v.im;
+    const z64 q = fQ ? VQ[idx] : ((row == kk) ? z64{1.0, 0.0} : z64{0.0, 0.0});
+    b_re[row * SLD + kk] = q.re;
+    b_im[row * SLD + kk] = q.im;
+  }
+  __syncthreads();
+  d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+  if (t < 256) mm32(a_re, a_im, b_re, b_im, false, accr, acci);  // X = T V_Q
+  __syncthreads();
+  if (t < 256)
+    for (int q = 0; q < 4; ++q) {
+      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
+      b_re[row * SLD + col] = accr[q];
+      b_im[row * SLD + col] = acci[q];
+      accr[q] = 0.0;
+      acci[q] = 0.0;
+    }
+#pragma unroll
+  for (int u = 0; u < BJ2 * BJ2 / kSolveThreads; ++u) {
+    const int idx = t + kSolveThreads * u;
+    a_re[(idx / BJ2) * SLD + idx % BJ2] = vp[u].re;
+    a_im[(idx / BJ2) * SLD + idx % BJ2] = vp[u].im;
+  }
+  __syncthreads();
+  if (t < 256) {
+    mm32(a_re, a_im, b_re, b_im, true, accr, acci);  // Y = V_P^H X
+    for (int q = 0; q < 4; ++q) {
+      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
+      const int gr = pair_index(P, row, step, nb), gc = pair_index(Q, col, step, nb);
+      Gp[(size_t)gr * mp + gc] = z64{accr[q], acci[q]};
+      if (P != Q) Gp[(size_t)gc * mp + gr] = z64{accr[q], -acci[q]};
+    }
+  }
+}
+
+// Kernel B of a round: tile blockIdx.x + tile0 of the round's updates, the G tiles (P, Q),
+// P <= Q, first, then the row tiles of the eigenvector accumulator; 512 threads.
+__global__ __launch_bounds__(512) void k_jblock_apply(z64* __restrict__ Gp, z64* __restrict__ Up, int mp, int nb,
+                                                      int step, const z64* __restrict__ V,
+                                                      const int* __restrict__ pair_flag, int tile0) {
+  __shared__ double a_re[BJ2 * SLD], a_im[BJ2 * SLD], b_re[BJ2 * SLD], b_im[BJ2 * SLD];
+  const int half = nb / 2, ngt = half * (half + 1) / 2;
+  const int tile = blockIdx.x + tile0;
+  if (tile < ngt)
+    g_tile(Gp, mp, nb, step, V, pair_flag, tile, a_re, a_im, b_re, b_im);
+  else
+    u_tile(Up, mp, nb, step, V, pair_flag, tile - ngt, a_re, a_im, b_re, b_im);
 }
 
 // Kernel A of a round: blocks 0..half-1 solve the sub-problems of outer step `step` (rotations
@@ -1011,7 +997,6 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   GC_HIP(hipMemcpyAsync(&trace, d_trace, sizeof(double), hipMemcpyDeviceToHost, s));
   GC_HIP(hipStreamSynchronize(s));
   const double thr = tol * trace, skipv = skip * trace, floor2 = (floor_rel * trace) * (floor_rel * trace);
-  const size_t lds_b = 4 * (size_t)BJ2 * SLD * sizeof(double);
   const int half = nb / 2;
   int sweeps = 0;
   bool conv = false;
@@ -1035,8 +1020,8 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
                          step, thr, tol, skipv, rel, floor2, vbuf(round), fbuf(round), w.flags, owe ? prev_step : -1,
                          owe ? vbuf(round - 1) : nullptr, owe ? fbuf(round - 1) : nullptr);
       GC_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_jblock_apply, dim3(defer ? gtiles : gtiles + utiles), dim3(256), lds_b, s, Gp, Up, mp, nb,
-                         step, vbuf(round), fbuf(round), 0);
+      hipLaunchKernelGGL(k_jblock_apply, dim3(defer ? gtiles : gtiles + utiles), dim3(kSolveThreads), 0, s, Gp, Up,
+                         mp, nb, step, vbuf(round), fbuf(round), 0);
       GC_LAUNCH_CHECK();
       prev_step = step;
     }
@@ -1052,8 +1037,8 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
     }
   }
   if (defer && round > 0) {  // the last round's U update
-    hipLaunchKernelGGL(k_jblock_apply, dim3(utiles), dim3(256), lds_b, s, Gp, Up, mp, nb, prev_step, vbuf(round - 1),
-                       fbuf(round - 1), gtiles);
+    hipLaunchKernelGGL(k_jblock_apply, dim3(utiles), dim3(kSolveThreads), 0, s, Gp, Up, mp, nb, prev_step,
+                       vbuf(round - 1), fbuf(round - 1), gtiles);
     GC_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_unpad, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gp, Up, m, mp, U, ldu, lam);
@@ -1062,15 +1047,6 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
            std::string("block Jacobi eigensolver did not converge (m = ") + std::to_string(m) +
                (rel ? ", relative-accuracy pass)" : ", first pass)"));
   if (host_sweeps) *host_sweeps = sweeps;
-}
-
-void linalg_set_attributes() {
-  // Large dynamic LDS for the Jacobi kernels; a failure here only means the default limit
-  // already allows it, so the sticky error state is cleared afterwards.
-  const int lim = 160 * 1024;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_jblock_apply), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lim);
-  (void)hipGetLastError();
 }
 
 void launch_rownorm2(hipStream_t s, const z64* B, int m, int k, int ldb, double* out) {
