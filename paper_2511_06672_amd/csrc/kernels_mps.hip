@@ -1,9 +1,11 @@
 // MPS-side kernels of the GCAMPS bottom loop (§2.4, §3):
 //  * block-MPO application of sum_b c_b P^b on the support of the commuted Weyl operator,
 //  * Theta <- Q Theta for the selected disentangler,
-//  * candidate scoring by the Renyi-2 purity of the two-site cut (FP64 or FP32), as a fused
-//    one-workgroup-per-candidate kernel for small cuts and a 64x64-tile MFMA kernel that
-//    generates the rotated rows on the fly for large cuts,
+//  * candidate scoring by the Renyi-2 purity of the two-site cut (FP64, FP32 or split BF16), as a
+//    fused one-workgroup-per-candidate kernel for small cuts; for large cuts the rotated
+//    matrices of a chunk of candidates are written to HBM and Hermitian Gram tiles on MFMA
+//    (128 x 128 FP32 and BF16 with direct-to-LDS loads, 64 x 64 FP64 for the re-score window)
+//    give sum |rho|^2,
 //  * FP64 selection (lowest index within tie_tol of the minimum) and the low-precision window,
 //  * dense helpers for the validation state vector.
 #include <algorithm>

@@ -132,6 +132,35 @@ def test_exact_workload_fp32_scoring_same_choices(g):
     assert aligned_error(st.statevector(), simulate(wl.circuit)) < 1e-10
 
 
+@pytest.mark.parametrize("d,n", [(5, 4), (7, 3)])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_scored"])
+def test_larger_prime_d_exact_regime(g, d, n, prec):
+    """d = 5 and 7 (tableau LUTs of 625 and 2401 entries, MPO bond d, d^2 x d^2 disentanglers):
+    choices and tableau bit-exact against the oracle, the state against the dense simulation."""
+    say(f"exact regime d={d} n={n} prec={prec}")
+    c = brickwork_circuit(d, n, 8, 6, seed=600 + d, parametrised=True, one_per_layer=False)
+    cands = candidate_words(d, 24, 600 + d)
+    st, orc = run_pair(g, c, cands, d ** (n // 2), 0.0, prec=prec, near_tie=1e-4)
+    assert np.array_equal(st.choice_log(), oracle_log(orc))
+    assert np.array_equal(st.tableau(), orc.tab.export())
+    assert aligned_error(st.statevector(), simulate(c)) < 1e-10
+
+
+@pytest.mark.parametrize("d,n", [(5, 8), (7, 6)])
+def test_larger_prime_d_truncated(g, d, n):
+    """d = 5 and 7 with chi_max = d and cutoff 1e-10: truncation, choices, bonds, tableau and
+    F_est against the oracle."""
+    say(f"truncated regime d={d} n={n} chi_max={d}")
+    c = brickwork_circuit(d, n, 10, 8, seed=610 + d, parametrised=True, one_per_layer=False)
+    cands = candidate_words(d, 24, 610 + d)
+    st, orc = run_pair(g, c, cands, d, 1e-10, near_tie=1e-4)
+    assert orc.f_est < 1.0
+    assert np.array_equal(st.choice_log(), oracle_log(orc))
+    assert st.bond_dims() == orc.mps.bond_dims()
+    assert np.array_equal(st.tableau(), orc.tab.export())
+    assert abs(st.fidelity() - orc.f_est) <= F_TOL * orc.f_est
+
+
 def test_truncated_regime_parity(g):
     """chi_max and cutoff active: choices, dims, tableau and F_est follow the oracle."""
     d, n = 3, 10

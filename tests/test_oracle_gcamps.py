@@ -27,6 +27,24 @@ def test_exact_workload_matches_statevector():
     assert any(e.choice for e in g.choice_log)          # the disentangler did act
 
 
+@pytest.mark.parametrize("d,n", [(5, 4), (7, 3)])
+def test_larger_prime_d_matches_statevector(d, n):
+    """d = 5 and 7 (the largest the library accepts): brickwork Cliffords, six phase gates with
+    seeded angles, disentangling on; the exact-regime state equals the dense simulation."""
+    c = brickwork_circuit(d, n, 8, 6, seed=600 + d, parametrised=True, one_per_layer=False)
+    cands = candidate_words(d, 24, 600 + d)
+    g = Gcamps(d, n, Config(chi_max=d ** (n // 2), cutoff=0.0), cands)
+    for layer in c.layers:
+        for b in layer.bricks:
+            g.apply_clifford(b.site, b.word.gens, b.word.weyl)
+        for ph in layer.phases:
+            g.apply_phase_rotation(ph.site, ph.phi)
+    psi, ref = g.statevector(), simulate(c)
+    ov = np.vdot(psi, ref)
+    assert np.max(np.abs(psi * ov / abs(ov) - ref)) < 1e-10
+    assert max(g.mps.bond_dims()) > 1 and len(g.choice_log) > 0
+
+
 def test_pure_clifford_circuit_keeps_product_state():
     c = brickwork_circuit(3, 6, 8, 0, seed=31)
     g = run_circuit(c, candidate_words(3, 16, 31), Config(chi_max=64, cutoff=0.0))
