@@ -33,8 +33,11 @@ struct EigWork {
   int* flags;  // device flags
   int m_pad;
 };
+// precheck: test every pair against the rotation criterion first and return U = I, lam =
+// diag(G) without a sweep when none qualifies (for matrices expected to be diagonal already,
+// e.g. a Rayleigh-Ritz step; the result equals what one sweep that rotates nothing leaves).
 void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu, double* lam,
-                   int rel, EigWork& w, DevStatus* st, int* host_sweeps);
+                   int rel, EigWork& w, DevStatus* st, int* host_sweeps, bool precheck = false);
 void launch_rownorm2(hipStream_t s, const z64* B, int m, int k, int ldb, double* out);
 // Sort, truncation rule, pass-2 decision.  mode 0 = truncate (cutoff, chi_max), 1 = floor only;
 // force_k > 0 keeps exactly that rank (frozen-decision replay).

@@ -9,6 +9,7 @@
 // * k_trunc: descending sort of squared singular values and the truncation rule.
 // * k_emit: writes the two factors of a split in the requested orientation.
 #include <cfloat>
+#include <cstring>
 
 #include "kernels.h"
 
@@ -736,7 +737,28 @@ __global__ void k_trace(const z64* __restrict__ Gp, int m, int mp, double* out) 
     if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    reinterpret_cast<int*>(out + 1)[0] = 0;  // pre-check flag, set by k_offdiag_check
+  }
+}
+
+// Pre-check of a decomposition: sets *flag when some pair (i < j < m) of Gp passes the rotation
+// test, with the thresholds the sweeps would use (from the trace in out[0] of k_trace).
+__global__ void k_offdiag_check(const z64* __restrict__ Gp, int m, int mp, const double* __restrict__ trace_in,
+                                double tol, double skip_rel, int rel, double floor_rel, int* __restrict__ flag) {
+  const double trace = *trace_in;
+  const JacobiArgs ja{tol * trace, tol, skip_rel * trace, rel, (floor_rel * trace) * (floor_rel * trace)};
+  const size_t total = (size_t)m * m;
+  int hit = 0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / m), j = (int)(e % m);
+    if (i < j) {
+      const z64 g = Gp[(size_t)i * mp + j];
+      if (rot_needed(Gp[(size_t)i * mp + i].re, Gp[(size_t)j * mp + j].re, g.re, g.im, ja)) hit = 1;
+    }
+  }
+  if (hit) atomicOr(flag, 1);
 }
 
 __global__ void k_unpad(const z64* __restrict__ Gp, const z64* __restrict__ Up, int m, int mp, z64* __restrict__ U,
@@ -959,7 +981,7 @@ void launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, const z6
 }
 
 void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu, double* lam, int rel, EigWork& w,
-                   DevStatus* st, int* host_sweeps) {
+                   DevStatus* st, int* host_sweeps, bool precheck) {
   const double tol = rel ? 1e-14 : 4e-15;
   // Relative pass: pairs whose diagonal entries are both below 1e-28 lambda_max (lambda_max >=
   // trace / m) are left alone.  They lie two decades below the rank floor (sigma^2 = 1e-26
@@ -993,9 +1015,23 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   double* d_trace = reinterpret_cast<double*>(w.flags + 512);
   hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, Gp, m, mp, d_trace);
   GC_LAUNCH_CHECK();
-  double trace = 0.0;
-  GC_HIP(hipMemcpyAsync(&trace, d_trace, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (precheck) {
+    hipLaunchKernelGGL(k_offdiag_check, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gp, m, mp, d_trace, tol,
+                       skip, rel, floor_rel, reinterpret_cast<int*>(d_trace + 1));
+    GC_LAUNCH_CHECK();
+  }
+  double tr_flag[2] = {0.0, 0.0};  // the trace and, after it, the pre-check flag
+  GC_HIP(hipMemcpyAsync(tr_flag, d_trace, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   GC_HIP(hipStreamSynchronize(s));
+  const double trace = tr_flag[0];
+  int pre_hit = 1;
+  std::memcpy(&pre_hit, &tr_flag[1], sizeof(int));
+  if (precheck && !pre_hit) {  // nothing to rotate: U = I (set by k_pad_copy), lam = diag(G)
+    hipLaunchKernelGGL(k_unpad, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gp, Up, m, mp, U, ldu, lam);
+    GC_LAUNCH_CHECK();
+    if (host_sweeps) *host_sweeps = 0;
+    return;
+  }
   const double thr = tol * trace, skipv = skip * trace, floor2 = (floor_rel * trace) * (floor_rel * trace);
   const int half = nb / 2;
   int sweeps = 0;
