@@ -255,12 +255,15 @@ struct gcamps_ctx {
       // Rayleigh-Ritz on the reduced basis: B B^H = U^H G U with the full Gram, so its
       // eigenvalues err by the square of the basis error where L L^H's err by tr S
       launch_zgemm(stream, 0, 1, nb, nb, kW, B, kW, B, kW, G, nb, one, 0, 1);
-      // nearly diagonal already: the pre-check usually finds nothing to rotate
+      // nearly diagonal already: the pre-check usually finds nothing to rotate, and then the
+      // eigenvectors are the identity and U and B stay as they are
       eig_hermitian(stream, G, nb, nb, Z, nb, lam, 0, eig, st, &sw_main, true);
-      launch_zgemm(stream, 0, 0, m, nb, nb, U, ldu, Z, nb, Utmp, ldu, one, 0, 0);
-      std::swap(U, Utmp);
-      launch_zgemm(stream, 1, 0, nb, kW, nb, Z, nb, B, kW, B2, kW, one, 0, 0);
-      std::swap(B, B2);
+      if (sw_main != 0) {
+        launch_zgemm(stream, 0, 0, m, nb, nb, U, ldu, Z, nb, Utmp, ldu, one, 0, 0);
+        std::swap(U, Utmp);
+        launch_zgemm(stream, 1, 0, nb, kW, nb, Z, nb, B, kW, B2, kW, one, 0, 0);
+        std::swap(B, B2);
+      }
     }
     // recorded decision: kept rank in the low bits, bit 30 = the accurate second pass ran
     int force_k = 0, force_pass2 = -1;
