@@ -286,16 +286,141 @@ __device__ __forceinline__ bool rot_params(double a, double b, double gr, double
   return true;
 }
 
+// One rotation of a parallel step: the pair's (c, sp) and new diagonal entries, and whether it
+// rotates at all.
+struct Rot {
+  double c, spr, spi, na, nb;
+  bool f;
+};
+
+// The rotation of pair (p, q) of the Hermitian matrix in planes (hr, hi) (leading dimension ld).
+__device__ __forceinline__ Rot pair_rot(const double* __restrict__ hr, const double* __restrict__ hi, int ld, int p,
+                                        int q, const JacobiArgs& ja) {
+  Rot r;
+  r.f = rot_params(hr[p * ld + p], hr[q * ld + q], hr[p * ld + q], hi[p * ld + q], ja, r.c, r.spr, r.spi, r.na, r.nb);
+  return r;
+}
+
+// The 2x2 block (a b; c d) of rows (p1, q1) and columns (p2, q2) of H, rotated in place into
+// the block of J H J^H: rotation r1 on the rows, r2 on the columns; diag marks the block of the
+// pair itself (r1 = r2), whose result is diagonal.
+__device__ __forceinline__ void rotate_vals(double& ar, double& ai, double& br, double& bi, double& cr, double& ci,
+                                            double& dr, double& di, const Rot& r1, const Rot& r2, bool diag,
+                                            int* any) {
+  if (r1.f) {  // rows: r_p' = c r_p - sp r_q ; r_q' = conj(sp) r_p + c r_q
+    const double c1 = r1.c, sp1r = r1.spr, sp1i = r1.spi;
+    const double nar = c1 * ar - (sp1r * cr - sp1i * ci), nai = c1 * ai - (sp1r * ci + sp1i * cr);
+    const double nbr = c1 * br - (sp1r * dr - sp1i * di), nbi = c1 * bi - (sp1r * di + sp1i * dr);
+    const double ncr = c1 * cr + (sp1r * ar + sp1i * ai), nci = c1 * ci + (sp1r * ai - sp1i * ar);
+    const double ndr = c1 * dr + (sp1r * br + sp1i * bi), ndi = c1 * di + (sp1r * bi - sp1i * br);
+    ar = nar;
+    ai = nai;
+    br = nbr;
+    bi = nbi;
+    cr = ncr;
+    ci = nci;
+    dr = ndr;
+    di = ndi;
+  }
+  if (r2.f) {  // cols: c_p' = c c_p - conj(sp) c_q ; c_q' = sp c_p + c c_q
+    const double c2 = r2.c, sp2r = r2.spr, sp2i = r2.spi;
+    const double nar = c2 * ar - (sp2r * br + sp2i * bi), nai = c2 * ai - (sp2r * bi - sp2i * br);
+    const double ncr = c2 * cr - (sp2r * dr + sp2i * di), nci = c2 * ci - (sp2r * di - sp2i * dr);
+    const double nbr = c2 * br + (sp2r * ar - sp2i * ai), nbi = c2 * bi + (sp2r * ai + sp2i * ar);
+    const double ndr = c2 * dr + (sp2r * cr - sp2i * ci), ndi = c2 * di + (sp2r * ci + sp2i * cr);
+    ar = nar;
+    ai = nai;
+    br = nbr;
+    bi = nbi;
+    cr = ncr;
+    ci = nci;
+    dr = ndr;
+    di = ndi;
+  }
+  if (diag && r1.f) {
+    ar = r1.na;
+    dr = r1.nb;
+    ai = di = br = bi = cr = ci = 0.0;
+  }
+  if (r1.f || r2.f) *any = 1;
+}
+
+// The same block read from the old planes (ir, ii) (leading dimension ld) and written to the new
+// ones (orr, oi).
+__device__ __forceinline__ void rotate_block(const double* __restrict__ ir, const double* __restrict__ ii,
+                                             double* __restrict__ orr, double* __restrict__ oi, int ld, int p1,
+                                             int q1, int p2, int q2, const Rot& r1, const Rot& r2, bool diag,
+                                             int* any) {
+  double ar = ir[p1 * ld + p2], ai = ii[p1 * ld + p2];
+  double br = ir[p1 * ld + q2], bi = ii[p1 * ld + q2];
+  double cr = ir[q1 * ld + p2], ci = ii[q1 * ld + p2];
+  double dr = ir[q1 * ld + q2], di = ii[q1 * ld + q2];
+  rotate_vals(ar, ai, br, bi, cr, ci, dr, di, r1, r2, diag, any);
+  orr[p1 * ld + p2] = ar;
+  oi[p1 * ld + p2] = ai;
+  orr[p1 * ld + q2] = br;
+  oi[p1 * ld + q2] = bi;
+  orr[q1 * ld + p2] = cr;
+  oi[q1 * ld + p2] = ci;
+  orr[q1 * ld + q2] = dr;
+  oi[q1 * ld + q2] = di;
+}
+
+// Rotation r (pair (p, q)) applied to rows v0 and v1 of the eigenvector accumulator, in place:
+// v_p' = c v_p - conj(sp) v_q ; v_q' = sp v_p + c v_q.
+__device__ __forceinline__ void rotate_vrows(double* __restrict__ vr, double* __restrict__ vi, int ld, int v0, int v1,
+                                             int p, int q, const Rot& r) {
+  const double c1 = r.c, sp1r = r.spr, sp1i = r.spi;
+  const double w0pr = vr[v0 * ld + p], w0pi = vi[v0 * ld + p];
+  const double w0qr = vr[v0 * ld + q], w0qi = vi[v0 * ld + q];
+  const double w1pr = vr[v1 * ld + p], w1pi = vi[v1 * ld + p];
+  const double w1qr = vr[v1 * ld + q], w1qi = vi[v1 * ld + q];
+  vr[v0 * ld + p] = c1 * w0pr - (sp1r * w0qr + sp1i * w0qi);
+  vi[v0 * ld + p] = c1 * w0pi - (sp1r * w0qi - sp1i * w0qr);
+  vr[v0 * ld + q] = c1 * w0qr + (sp1r * w0pr - sp1i * w0pi);
+  vi[v0 * ld + q] = c1 * w0qi + (sp1r * w0pi + sp1i * w0pr);
+  vr[v1 * ld + p] = c1 * w1pr - (sp1r * w1qr + sp1i * w1qi);
+  vi[v1 * ld + p] = c1 * w1pi - (sp1r * w1qi - sp1i * w1qr);
+  vr[v1 * ld + q] = c1 * w1qr + (sp1r * w1pr - sp1i * w1pi);
+  vi[v1 * ld + q] = c1 * w1qi + (sp1r * w1pi + sp1i * w1pr);
+}
+
+// rot_params without branches: every lane computes the rotation and the result is selected at the
+// end (the identity and the unchanged diagonal when the pair is not rotated), so that the
+// scheduler can interleave two rotations of one thread.
+__device__ __forceinline__ Rot rot_select(double a, double b, double gr, double gi, const JacobiArgs& ja) {
+  const bool need = rot_needed(a, b, gr, gi, ja);
+  const double h2 = gr * gr + gi * gi;
+  const double dlt = b - a;
+  const double sg = dlt < 0.0 ? -1.0 : 1.0;
+  const double r2 = dlt * dlt + 4.0 * h2;
+  const double den = fabs(dlt) + r2 * rsqrt_nr(r2);
+  const double q = rsqrt_nr(den * den + 4.0 * h2);
+  const double f = 2.0 * sg * q;
+  const double th = 2.0 * sg * h2 * rcp_nr(den);
+  Rot r;
+  r.f = need;
+  r.c = need ? den * q : 1.0;
+  r.spr = need ? f * gr : 0.0;
+  r.spi = need ? f * gi : 0.0;
+  r.na = need ? a - th : a;
+  r.nb = need ? b + th : b;
+  return r;
+}
+
 // A sequence of parallel Jacobi steps on the Hermitian H (2*half indices, half <= 16) held as
 // two re/im plane pairs in LDS (double buffer).  Step s uses the pairs tab[s][k] = (p, q).
 // Item (k1, k2) (k1, k2 < half) is the 2x2 block of rows (p_k1, q_k1) and columns
 // (p_k2, q_k2): it needs rotations k1 and k2, computed from the old buffer, and its rotated block
-// goes to the new buffer.  Rotation k1 is also applied to rows 2 k2 and 2 k2 + 1 of the
-// eigenvector accumulator (V planes, in place; 2 * half rows in total).  With at least
-// 2 half^2 threads the block update and the V update of an item run on different threads
-// (each computes the rotations it needs), otherwise one thread does both; items are dealt
-// round-robin.  One barrier per step.  Returns the index (0/1) of the buffer holding the result;
-// *any is set when a rotation happened.
+// goes to the new buffer.  Rotation k1 is also applied to two rows of the eigenvector
+// accumulator (V planes, in place; 2 * half rows in total).  With at least 2 half^2 threads the
+// block update and the V update of an item run on different threads (each computes the
+// rotations it needs), otherwise one thread does both; items are dealt round-robin.  On that
+// split, V threads take k1 as the fast index and rows k2 and k2 + half (with a leading
+// dimension of 16 mod 32 doubles the V accesses of 32 consecutive lanes fall in distinct
+// banks); otherwise k2 is the fast index and the rows are 2 k2 and 2 k2 + 1.  One barrier per
+// step.  Returns the index (0/1) of the buffer holding the result; *any is set when a rotation
+// happened.
 __device__ int jacobi_steps(double* __restrict__ h0r, double* __restrict__ h0i, double* __restrict__ h1r,
                             double* __restrict__ h1i, int ldh, int half, const unsigned char* __restrict__ tab,
                             int nsteps, double* __restrict__ vr, double* __restrict__ vi, int ldv,
@@ -312,82 +437,30 @@ __device__ int jacobi_steps(double* __restrict__ h0r, double* __restrict__ h0i, 
     double* __restrict__ orr = cur ? h0r : h1r;
     double* __restrict__ oi = cur ? h0i : h1i;
     for (int e0 = t; e0 < nwork; e0 += nt) {
-      const bool do_v = !split || e0 >= nitems;
+      const bool vsplit = split && e0 >= nitems;
+      const bool do_v = !split || vsplit;
       const bool do_h = !split || e0 < nitems;
-      const int e = (split && e0 >= nitems) ? e0 - nitems : e0;
-      const int k1 = (int)(((float)e + 0.5f) / (float)half);
-      const int k2 = e - k1 * half;
+      const int e = vsplit ? e0 - nitems : e0;
+      int k1, k2;
+      if (vsplit) {
+        k2 = (int)(((float)e + 0.5f) / (float)half);
+        k1 = e - k2 * half;
+      } else {
+        k1 = (int)(((float)e + 0.5f) / (float)half);
+        k2 = e - k1 * half;
+      }
       const int p1 = pt[2 * k1], q1 = pt[2 * k1 + 1];
-      const double a1 = ir[p1 * ldh + p1], b1 = ir[q1 * ldh + q1], g1r = ir[p1 * ldh + q1], g1i = ii[p1 * ldh + q1];
-      double c1, sp1r, sp1i, na1, nb1;
-      const bool f1 = rot_params(a1, b1, g1r, g1i, ja, c1, sp1r, sp1i, na1, nb1);
+      const Rot r1 = pair_rot(ir, ii, ldh, p1, q1, ja);
       if (do_h) {
         const int p2 = pt[2 * k2], q2 = pt[2 * k2 + 1];
-        const double a2 = ir[p2 * ldh + p2], b2 = ir[q2 * ldh + q2], g2r = ir[p2 * ldh + q2],
-                     g2i = ii[p2 * ldh + q2];
-        double ar = ir[p1 * ldh + p2], ai = ii[p1 * ldh + p2];
-        double br = ir[p1 * ldh + q2], bi = ii[p1 * ldh + q2];
-        double cr = ir[q1 * ldh + p2], ci = ii[q1 * ldh + p2];
-        double dr = ir[q1 * ldh + q2], di = ii[q1 * ldh + q2];
-        double c2, sp2r, sp2i, na2, nb2;
-        const bool f2 = rot_params(a2, b2, g2r, g2i, ja, c2, sp2r, sp2i, na2, nb2);
-        if (f1) {  // rows: r_p' = c r_p - sp r_q ; r_q' = conj(sp) r_p + c r_q
-          const double nar = c1 * ar - (sp1r * cr - sp1i * ci), nai = c1 * ai - (sp1r * ci + sp1i * cr);
-          const double nbr = c1 * br - (sp1r * dr - sp1i * di), nbi = c1 * bi - (sp1r * di + sp1i * dr);
-          const double ncr = c1 * cr + (sp1r * ar + sp1i * ai), nci = c1 * ci + (sp1r * ai - sp1i * ar);
-          const double ndr = c1 * dr + (sp1r * br + sp1i * bi), ndi = c1 * di + (sp1r * bi - sp1i * br);
-          ar = nar;
-          ai = nai;
-          br = nbr;
-          bi = nbi;
-          cr = ncr;
-          ci = nci;
-          dr = ndr;
-          di = ndi;
-        }
-        if (f2) {  // cols: c_p' = c c_p - conj(sp) c_q ; c_q' = sp c_p + c c_q
-          const double nar = c2 * ar - (sp2r * br + sp2i * bi), nai = c2 * ai - (sp2r * bi - sp2i * br);
-          const double ncr = c2 * cr - (sp2r * dr + sp2i * di), nci = c2 * ci - (sp2r * di - sp2i * dr);
-          const double nbr = c2 * br + (sp2r * ar - sp2i * ai), nbi = c2 * bi + (sp2r * ai + sp2i * ar);
-          const double ndr = c2 * dr + (sp2r * cr - sp2i * ci), ndi = c2 * di + (sp2r * ci + sp2i * cr);
-          ar = nar;
-          ai = nai;
-          br = nbr;
-          bi = nbi;
-          cr = ncr;
-          ci = nci;
-          dr = ndr;
-          di = ndi;
-        }
-        if (k1 == k2 && f1) {
-          ar = na1;
-          dr = nb1;
-          ai = di = br = bi = cr = ci = 0.0;
-        }
-        if (f1 || f2) *any = 1;
-        orr[p1 * ldh + p2] = ar;
-        oi[p1 * ldh + p2] = ai;
-        orr[p1 * ldh + q2] = br;
-        oi[p1 * ldh + q2] = bi;
-        orr[q1 * ldh + p2] = cr;
-        oi[q1 * ldh + p2] = ci;
-        orr[q1 * ldh + q2] = dr;
-        oi[q1 * ldh + q2] = di;
+        const Rot r2 = pair_rot(ir, ii, ldh, p2, q2, ja);
+        rotate_block(ir, ii, orr, oi, ldh, p1, q1, p2, q2, r1, r2, k1 == k2, any);
       }
-      if (do_v && f1) {  // V columns (p1, q1), rows v0, v1: v_p' = c v_p - conj(sp) v_q ; v_q' = sp v_p + c v_q
-        const int v0 = 2 * k2, v1 = 2 * k2 + 1;
-        const double w0pr = vr[v0 * ldv + p1], w0pi = vi[v0 * ldv + p1];
-        const double w0qr = vr[v0 * ldv + q1], w0qi = vi[v0 * ldv + q1];
-        const double w1pr = vr[v1 * ldv + p1], w1pi = vi[v1 * ldv + p1];
-        const double w1qr = vr[v1 * ldv + q1], w1qi = vi[v1 * ldv + q1];
-        vr[v0 * ldv + p1] = c1 * w0pr - (sp1r * w0qr + sp1i * w0qi);
-        vi[v0 * ldv + p1] = c1 * w0pi - (sp1r * w0qi - sp1i * w0qr);
-        vr[v0 * ldv + q1] = c1 * w0qr + (sp1r * w0pr - sp1i * w0pi);
-        vi[v0 * ldv + q1] = c1 * w0qi + (sp1r * w0pi + sp1i * w0pr);
-        vr[v1 * ldv + p1] = c1 * w1pr - (sp1r * w1qr + sp1i * w1qi);
-        vi[v1 * ldv + p1] = c1 * w1pi - (sp1r * w1qi - sp1i * w1qr);
-        vr[v1 * ldv + q1] = c1 * w1qr + (sp1r * w1pr - sp1i * w1pi);
-        vi[v1 * ldv + q1] = c1 * w1qi + (sp1r * w1pi + sp1i * w1pr);
+      if (do_v && r1.f) {
+        if (vsplit)
+          rotate_vrows(vr, vi, ldv, k2, k2 + half, p1, q1, r1);
+        else
+          rotate_vrows(vr, vi, ldv, 2 * k2, 2 * k2 + 1, p1, q1, r1);
       }
     }
     __syncthreads();
@@ -396,17 +469,97 @@ __device__ int jacobi_steps(double* __restrict__ h0r, double* __restrict__ h0i, 
   return cur;
 }
 
-// Round-robin table for mp indices (mp - 1 steps of mp/2 pairs).
-__device__ void build_rr_table(unsigned char* tab, int mp) { build_pair_table(tab, mp); }
+// x from lane (l + 1) mod 16 of the same 16-lane row (DPP row rotation by 15 to the right); every
+// lane of the row must be active.
+__device__ __forceinline__ double row_next(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, 0x12F, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x12F, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
-// Inter-block table of a 2h-index pair problem: step s pairs k with h + (k + s) mod h.
-__device__ void build_ib_table(unsigned char* tab, int h) {
-  for (int e = threadIdx.x; e < h * h; e += blockDim.x) {
-    const int s = e / h, k = e - s * h;
-    tab[2 * e] = (unsigned char)k;
-    tab[2 * e + 1] = (unsigned char)(h + (k + s) % h);
+// The inter-block steps of a 32-index sub-problem on 512 threads, with its eigenvector
+// accumulator V (starting from the identity) written to vo (32 x 32, row-major): step s
+// (0..15) pairs index k < 16 with q_k(s) = 16 + (k + s) mod 16, so the 16 steps visit every pair
+// (i < 16 <= j) once.  The arithmetic is that of jacobi_steps on the same pairs.
+// Threads 0..255 update the blocks (k1 = t / 16, k2 = t mod 16); all LDS reads of a step are
+// issued before its rotations are computed.  With a leading dimension of 16 mod 32 doubles every
+// block and diagonal access of 32 consecutive lanes falls in distinct LDS banks.
+// Threads 256..511 hold V in registers: thread (k1 = t mod 16, k2 = (t - 256) / 16) keeps rows
+// k2 and k2 + 16 of columns k1 and q_k1(s).  It applies rotation k1, then takes column
+// q_k1(s + 1) = q_{k1+1}(s) from the next lane of its 16-lane row; after 16 steps the columns
+// are back at 16 + k1.  The 16 steps leave the matrix in (h0r, h0i).
+__device__ void jacobi_ib_steps(double* __restrict__ h0r, double* __restrict__ h0i, double* __restrict__ h1r,
+                                double* __restrict__ h1i, int ld, z64* __restrict__ vo, const JacobiArgs& ja,
+                                int* any) {
+  const int t = threadIdx.x;
+  const bool do_v = t >= 256;  // uniform over each wave
+  const int e = t & 255;
+  const int k1 = do_v ? (e & 15) : (e >> 4);
+  const int k2 = do_v ? (e >> 4) : (e & 15);
+  // V thread: columns (p, q) of rows k2 (w0*) and k2 + 16 (w1*)
+  double w0pr = (k1 == k2) ? 1.0 : 0.0, w0pi = 0.0, w0qr = 0.0, w0qi = 0.0;
+  double w1pr = 0.0, w1pi = 0.0, w1qr = (k1 == k2) ? 1.0 : 0.0, w1qi = 0.0;
+#pragma unroll 2
+  for (int step = 0; step < 16; ++step) {
+    const bool odd = step & 1;
+    const double* __restrict__ ir = odd ? h1r : h0r;
+    const double* __restrict__ ii = odd ? h1i : h0i;
+    double* __restrict__ orr = odd ? h0r : h1r;
+    double* __restrict__ oi = odd ? h0i : h1i;
+    const int p1 = k1, q1 = 16 + ((k1 + step) & 15);
+    const double a1 = ir[p1 * ld + p1], b1 = ir[q1 * ld + q1], g1r = ir[p1 * ld + q1], g1i = ii[p1 * ld + q1];
+    if (!do_v) {
+      const int p2 = k2, q2 = 16 + ((k2 + step) & 15);
+      const double a2 = ir[p2 * ld + p2], b2 = ir[q2 * ld + q2], g2r = ir[p2 * ld + q2], g2i = ii[p2 * ld + q2];
+      double ar = ir[p1 * ld + p2], ai = ii[p1 * ld + p2];
+      double br = ir[p1 * ld + q2], bi = ii[p1 * ld + q2];
+      double cr = ir[q1 * ld + p2], ci = ii[q1 * ld + p2];
+      double dr = ir[q1 * ld + q2], di = ii[q1 * ld + q2];
+      const Rot r1 = rot_select(a1, b1, g1r, g1i, ja), r2 = rot_select(a2, b2, g2r, g2i, ja);
+      rotate_vals(ar, ai, br, bi, cr, ci, dr, di, r1, r2, k1 == k2, any);
+      orr[p1 * ld + p2] = ar;
+      oi[p1 * ld + p2] = ai;
+      orr[p1 * ld + q2] = br;
+      oi[p1 * ld + q2] = bi;
+      orr[q1 * ld + p2] = cr;
+      oi[q1 * ld + p2] = ci;
+      orr[q1 * ld + q2] = dr;
+      oi[q1 * ld + q2] = di;
+    } else {
+      const Rot r1 = rot_select(a1, b1, g1r, g1i, ja);
+      if (r1.f) {  // v_p' = c v_p - conj(sp) v_q ; v_q' = sp v_p + c v_q
+        const double c1 = r1.c, sp1r = r1.spr, sp1i = r1.spi;
+        const double n0pr = c1 * w0pr - (sp1r * w0qr + sp1i * w0qi), n0pi = c1 * w0pi - (sp1r * w0qi - sp1i * w0qr);
+        const double n0qr = c1 * w0qr + (sp1r * w0pr - sp1i * w0pi), n0qi = c1 * w0qi + (sp1r * w0pi + sp1i * w0pr);
+        const double n1pr = c1 * w1pr - (sp1r * w1qr + sp1i * w1qi), n1pi = c1 * w1pi - (sp1r * w1qi - sp1i * w1qr);
+        const double n1qr = c1 * w1qr + (sp1r * w1pr - sp1i * w1pi), n1qi = c1 * w1qi + (sp1r * w1pi + sp1i * w1pr);
+        w0pr = n0pr;
+        w0pi = n0pi;
+        w0qr = n0qr;
+        w0qi = n0qi;
+        w1pr = n1pr;
+        w1pi = n1pi;
+        w1qr = n1qr;
+        w1qi = n1qi;
+      }
+      w0qr = row_next(w0qr);
+      w0qi = row_next(w0qi);
+      w1qr = row_next(w1qr);
+      w1qi = row_next(w1qi);
+    }
+    __syncthreads();
+  }
+  if (do_v) {
+    vo[k2 * 32 + k1] = z64{w0pr, w0pi};
+    vo[k2 * 32 + 16 + k1] = z64{w0qr, w0qi};
+    vo[(k2 + 16) * 32 + k1] = z64{w1pr, w1pi};
+    vo[(k2 + 16) * 32 + 16 + k1] = z64{w1qr, w1qi};
   }
 }
+
+// Round-robin table for mp indices (mp - 1 steps of mp/2 pairs).
+__device__ void build_rr_table(unsigned char* tab, int mp) { build_pair_table(tab, mp); }
 
 constexpr int SMALL_LD = 33;  // plane leading dimension for sub-problems of up to 32 indices
 
@@ -494,14 +647,16 @@ __global__ __launch_bounds__(256) void k_jacobi_small(const z64* __restrict__ G,
 // ----------------------------------------------------------------------- block Jacobi
 constexpr int BJ = kBlk;      // block size (16)
 constexpr int kSolveThreads = 512;  // threads per 32x32 sub-problem (block and V updates split)
+static_assert(kSolveThreads == 2 * BJ * BJ, "the inter-block steps give each thread one block or one V item");
 constexpr int BJ2 = 2 * kBlk; // pair size (32)
-constexpr int SLD = BJ2 + 1;  // LDS leading dimension (plane layout)
+constexpr int SLD = BJ2 + 1;  // LDS leading dimension of the product tiles (plane layout)
+constexpr int JLD = 48;       // LDS leading dimension of the solve's planes (16 mod 32 doubles)
 
 // Solve step of a round: pair k of outer step `step` solves its 32x32 sub-problem (blocks I, J)
 // and writes the accumulated rotation to V + k*32*32 (row-major) with a rotated flag.  The first
 // step of an outer sweep runs a full round-robin sweep over the 32 indices (covering the pairs
 // inside each block); later steps rotate only the 16 x 16 inter-block pairs.  Over one outer
-// sweep every index pair is visited once.  LDS: six 32 x SLD planes.
+// sweep every index pair is visited once.  LDS: six 32 x JLD planes.
 __device__ void solve_pair(int k, const z64* __restrict__ Gp, int mp, int nb, int step, double thr, double tol,
                            double skip, int rel, double floor2, z64* __restrict__ Vout, int* __restrict__ pair_flag,
                            int* __restrict__ any_flag, double* __restrict__ h0r, double* __restrict__ h0i,
@@ -515,36 +670,37 @@ __device__ void solve_pair(int k, const z64* __restrict__ Gp, int mp, int nb, in
     any = 0;
     need = 0;
   }
-  if (full)
-    build_rr_table(tab, BJ2);
-  else
-    build_ib_table(tab, BJ);
+  if (full) build_rr_table(tab, BJ2);
   const JacobiArgs ja{thr, tol, skip, rel, floor2};
   for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
     const int i = idx / BJ2, j = idx % BJ2;
     const int gi = (i < BJ ? I * BJ + i : J * BJ + (i - BJ));
     const int gj = (j < BJ ? I * BJ + j : J * BJ + (j - BJ));
     const z64 v = Gp[(size_t)gi * mp + gj];
-    h0r[i * SLD + j] = v.re;
-    h0i[i * SLD + j] = v.im;
-    vr[i * SLD + j] = (i == j) ? 1.0 : 0.0;
-    vi[i * SLD + j] = 0.0;
+    h0r[i * JLD + j] = v.re;
+    h0i[i * JLD + j] = v.im;
+    vr[i * JLD + j] = (i == j) ? 1.0 : 0.0;
+    vi[i * JLD + j] = 0.0;
   }
   __syncthreads();
   for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
     const int i = idx / BJ2, j = idx % BJ2;
     if (i < j && (full || (i < BJ && j >= BJ))) {
-      if (rot_needed(h0r[i * SLD + i], h0r[j * SLD + j], h0r[i * SLD + j], h0i[i * SLD + j], ja)) need = 1;
+      if (rot_needed(h0r[i * JLD + i], h0r[j * JLD + j], h0r[i * JLD + j], h0i[i * JLD + j], ja)) need = 1;
     }
   }
   __syncthreads();
   const int run = need;
   if (run) {
-    jacobi_steps(h0r, h0i, h1r, h1i, SLD, BJ, tab, full ? BJ2 - 1 : BJ, vr, vi, SLD, ja, &any);
     z64* vo = Vout + (size_t)k * BJ2 * BJ2;
-    for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
-      const int i = idx / BJ2, j = idx % BJ2;
-      vo[idx] = z64{vr[i * SLD + j], vi[i * SLD + j]};
+    if (full) {
+      jacobi_steps(h0r, h0i, h1r, h1i, JLD, BJ, tab, BJ2 - 1, vr, vi, JLD, ja, &any);
+      for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+        const int i = idx / BJ2, j = idx % BJ2;
+        vo[idx] = z64{vr[i * JLD + j], vi[i * JLD + j]};
+      }
+    } else {
+      jacobi_ib_steps(h0r, h0i, h1r, h1i, JLD, vo, ja, &any);
     }
   }
   if (t == 0) {
@@ -706,7 +862,7 @@ __global__ __launch_bounds__(512) void k_jblock_solve(const z64* __restrict__ Gp
                                                       int* __restrict__ any_flag, int ustep,
                                                       const z64* __restrict__ Vprev,
                                                       const int* __restrict__ pflag_prev) {
-  constexpr int PL = BJ2 * SLD;
+  constexpr int PL = BJ2 * JLD;  // the row tiles of u_tile (32 x SLD) fit in the first four planes
   __shared__ double h0r[PL], h0i[PL], h1r[PL], h1i[PL], vr[PL], vi[PL];
   __shared__ unsigned char tab[31 * 32];
   __shared__ int any, need;
