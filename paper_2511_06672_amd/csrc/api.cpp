@@ -129,7 +129,7 @@ Layout make_layout(const gcamps_config& c) {
   L.off_sig = take(L.mcap * sizeof(double));
   L.off_lam = take(L.mcap * sizeof(double));
   L.off_perm = take(L.mcap * sizeof(int));
-  L.off_eigG = take(2 * L.m_pad * L.m_pad * sizeof(z64));
+  L.off_eigG = take(3 * L.m_pad * L.m_pad * sizeof(z64));  // two matrix buffers and the accumulator
   L.off_eigV = take((L.m_pad / 64 + 1) * 64 * 64 * sizeof(z64));
   L.off_flags = take(4096);
   L.off_s2 = take(L.ncand * sizeof(double));

@@ -28,7 +28,7 @@ void launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, const z6
 // the rotated matrix, padded to mp x mp with ld mp in the block variant); U (ld ldu) receives
 // eigenvectors, lam the eigenvalues (unsorted).  rel: relative-accuracy criterion.
 struct EigWork {
-  z64* G;      // padded m_pad x m_pad scratch
+  z64* G;      // three padded m_pad x m_pad planes: matrix, accumulator, second matrix buffer
   z64* V;      // block rotations
   int* flags;  // device flags
   int m_pad;

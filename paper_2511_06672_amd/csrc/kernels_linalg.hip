@@ -214,9 +214,12 @@ __global__ __launch_bounds__(512) void k_zgemm_ks(int M, int N, int K, const z64
 // is fixed, position i >= 1 holds element ((i - 1 + s) mod (mp - 1)) + 1.  Every unordered pair
 // of the mp indices meets exactly once per sweep.
 __device__ __forceinline__ void rr_pair(int k, int s, int mp, int& p, int& q) {
-  int i0 = k, i1 = mp - 1 - k;
-  int e0 = (i0 == 0) ? 0 : ((i0 - 1 + s) % (mp - 1)) + 1;
-  int e1 = ((i1 - 1 + s) % (mp - 1)) + 1;
+  // k < mp / 2 and 0 <= s < mp - 1 keep both circle positions below 2 (mp - 1): one conditional
+  // subtraction reduces them
+  const int n1 = mp - 1, i0 = k, i1 = mp - 1 - k;
+  const int x0 = i0 - 1 + s, x1 = i1 - 1 + s;
+  int e0 = (i0 == 0) ? 0 : (x0 >= n1 ? x0 - n1 : x0) + 1;
+  int e1 = (x1 >= n1 ? x1 - n1 : x1) + 1;
   p = e0 < e1 ? e0 : e1;
   q = e0 < e1 ? e1 : e0;
 }
@@ -652,12 +655,326 @@ constexpr int BJ2 = 2 * kBlk; // pair size (32)
 constexpr int SLD = BJ2 + 1;  // LDS leading dimension of the product tiles (plane layout)
 constexpr int JLD = 48;       // LDS leading dimension of the solve's planes (16 mod 32 doubles)
 
+// One 16x16 quadrant of a 32-deep complex product on one wave: acc += A B with
+// A(row, kk) = a[kk * lda + wr + row] (conjugated when conja) and B(kk, col) = b[kk * ldb + wc + col].
+// Every quadrant product of the rounds goes through this sequence, so a quadrant computed on its
+// own equals the same quadrant of a whole-tile product bit for bit.
+__device__ __forceinline__ void mmq(const double* ar_, const double* ai_, int lda, int wr, const double* br_,
+                                    const double* bi_, int ldb, int wc, bool conja, d4& accr, d4& acci) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int kk = 0; kk < BJ2; kk += 4) {
+    const int ka = kk + (lane >> 4);
+    const double ar = ar_[ka * lda + wr + (lane & 15)];
+    const double ai = conja ? -ai_[ka * lda + wr + (lane & 15)] : ai_[ka * lda + wr + (lane & 15)];
+    const double br = br_[ka * ldb + wc + (lane & 15)];
+    const double bi = bi_[ka * ldb + wc + (lane & 15)];
+    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, accr, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, acci, 0, 0, 0);
+  }
+}
+
+// 32x32x32 complex product on four waves (one 16x16 quadrant each): acc += A * B where A is
+// read as a[kk][row] (planes re/im, ld SLD) and B as b[kk][col]; conja conjugates A.
+__device__ __forceinline__ void mm32(const double* ar_, const double* ai_, const double* br_, const double* bi_,
+                                     bool conja, d4& accr, d4& acci) {
+  const int w = threadIdx.x >> 6;
+  mmq(ar_, ai_, SLD, (w >> 1) * 16, br_, bi_, SLD, (w & 1) * 16, conja, accr, acci);
+}
+
+__device__ __forceinline__ int pair_index(int P, int i, int step, int nb) {
+  int I, J;
+  rr_pair(P, step, nb, I, J);
+  return i < BJ ? I * BJ + i : J * BJ + (i - BJ);
+}
+
+// The pair holding block b at outer step s and b's offset in it (0: first block, BJ: second):
+// the inverse of rr_pair over nb blocks.  Block 0 stays in pair 0; another block b sits at
+// position x = (b - 1 - s) mod (nb - 1) of the rotating circle, which is the first slot of pair
+// x + 1 for x < nb / 2 - 1 and the second slot of pair nb - 2 - x otherwise.
+__device__ __forceinline__ void block_home(int b, int s, int nb, int& pair, int& off) {
+  if (b == 0) {
+    pair = 0;
+    off = 0;
+    return;
+  }
+  int x = b - 1 - s;  // in (-(nb - 1), nb - 1)
+  if (x < 0) x += nb - 1;
+  pair = (x <= nb / 2 - 2) ? x + 1 : nb - 2 - x;
+  int I, J;
+  rr_pair(pair, s, nb, I, J);
+  off = (b == I) ? 0 : BJ;
+}
+
+// One 32x32 row tile (R, Q) of U <- U V_Q with 512 threads: all threads stage the operands, the
+// first four waves multiply (planes re/im in a_*/b_*, 32 x SLD each).
+__device__ void u_tile(z64* __restrict__ Up, int mp, int nb, int step, const z64* __restrict__ V,
+                       const int* __restrict__ pair_flag, int tile, double* __restrict__ a_re,
+                       double* __restrict__ a_im, double* __restrict__ b_re, double* __restrict__ b_im) {
+  const int half = nb / 2;
+  const int R = tile / half, Q = tile % half;
+  if (!pair_flag[Q]) return;  // uniform over the block
+  const int t = threadIdx.x;
+  const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
+  int q0, q1;
+  rr_pair(Q, step, nb, q0, q1);
+  z64 uv[BJ2 * BJ2 / kSolveThreads], qv[BJ2 * BJ2 / kSolveThreads];
+#pragma unroll
+  for (int u = 0; u < BJ2 * BJ2 / kSolveThreads; ++u) {  // every load before the first store
+    const int idx = t + kSolveThreads * u, row = idx / BJ2, kk = idx % BJ2;
+    uv[u] = Up[(size_t)(R * BJ2 + row) * mp + (kk < BJ ? q0 * BJ + kk : q1 * BJ + kk - BJ)];
+    qv[u] = VQ[idx];
+  }
+#pragma unroll
+  for (int u = 0; u < BJ2 * BJ2 / kSolveThreads; ++u) {
+    const int idx = t + kSolveThreads * u, row = idx / BJ2, kk = idx % BJ2;
+    a_re[kk * SLD + row] = uv[u].re;
+    a_im[kk * SLD + row] = uv[u].im;
+    b_re[row * SLD + kk] = qv[u].re;
+    b_im[row * SLD + kk] = qv[u].im;
+  }
+  __syncthreads();
+  if (t < 256) {
+    const int lane = t & 63, w = t >> 6;
+    const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+    d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+    mm32(a_re, a_im, b_re, b_im, false, accr, acci);
+    for (int q = 0; q < 4; ++q) {
+      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
+      Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, col, step, nb)] = z64{accr[q], acci[q]};
+    }
+  }
+}
+
+// One 32x32 tile (P, Q), P <= Q, of the round's update Gd = V^H Gs V with 512 threads (all stage
+// the operands, the first four waves multiply); the (Q, P) tile is written as the conjugate
+// transpose.  A pair that did not rotate contributes the identity; a tile whose two pairs both
+// did not rotate is copied as it is (with its mirror).
+__device__ void g_tile(const z64* __restrict__ Gs, z64* __restrict__ Gd, int mp, int nb, int step,
+                       const z64* __restrict__ V, const int* __restrict__ pair_flag, int tile, double* __restrict__ a_re,
+                       double* __restrict__ a_im, double* __restrict__ b_re, double* __restrict__ b_im) {
+  const int half = nb / 2;
+  int P = 0, rem = tile;
+  while (rem >= half - P) {
+    rem -= half - P;
+    ++P;
+  }
+  const int Q = P + rem;
+  const int fP = pair_flag[P], fQ = pair_flag[Q];
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, w = t >> 6;
+  if (!fP && !fQ) {  // uniform over the block
+    for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+      const int row = idx / BJ2, col = idx % BJ2;
+      const size_t pq = (size_t)pair_index(P, row, step, nb) * mp + pair_index(Q, col, step, nb);
+      const size_t qp = (size_t)pair_index(Q, row, step, nb) * mp + pair_index(P, col, step, nb);
+      Gd[pq] = Gs[pq];
+      if (P != Q) Gd[qp] = Gs[qp];
+    }
+    return;
+  }
+  const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+  const z64* VP = V + (size_t)P * BJ2 * BJ2;
+  const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
+  // V_P is needed after the first product: fetch it into registers now
+  z64 vp[BJ2 * BJ2 / kSolveThreads];
+#pragma unroll
+  for (int u = 0; u < BJ2 * BJ2 / kSolveThreads; ++u) {
+    const int idx = t + kSolveThreads * u;
+    const int r = idx / BJ2, c = idx % BJ2;
+    vp[u] = fP ? VP[idx] : ((r == c) ? z64{1.0, 0.0} : z64{0.0, 0.0});
+  }
+  // a[kk][row] = T[row][kk] = Gs[rows(P)[row], cols(Q)[kk]];  b = V_Q (or the identity); every
+  // load is issued before the first store
+  int p0, p1, q0, q1;
+  rr_pair(P, step, nb, p0, p1);
+  rr_pair(Q, step, nb, q0, q1);
+  z64 gv[BJ2 * BJ2 / kSolveThreads], qv[BJ2 * BJ2 / kSolveThreads];
+#pragma unroll
+  for (int u = 0; u < BJ2 * BJ2 / kSolveThreads; ++u) {
+    const int idx = t + kSolveThreads * u, row = idx / BJ2, kk = idx % BJ2;
+    const int gr = row < BJ ? p0 * BJ + row : p1 * BJ + row - BJ;
+    const int gc = kk < BJ ? q0 * BJ + kk : q1 * BJ + kk - BJ;
+    gv[u] = Gs[(size_t)gr * mp + gc];
+    qv[u] = fQ ? VQ[idx] : ((row == kk) ? z64{1.0, 0.0} : z64{0.0, 0.0});
+  }
+#pragma unroll
+  for (int u = 0; u < BJ2 * BJ2 / kSolveThreads; ++u) {
+    const int idx = t + kSolveThreads * u, row = idx / BJ2, kk = idx % BJ2;
+    a_re[kk * SLD + row] = gv[u].re;
+    a_im[kk * SLD + row] = gv[u].im;
+    b_re[row * SLD + kk] = qv[u].re;
+    b_im[row * SLD + kk] = qv[u].im;
+  }
+  __syncthreads();
+  d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+  if (t < 256) mm32(a_re, a_im, b_re, b_im, false, accr, acci);  // X = T V_Q
+  __syncthreads();
+  if (t < 256)
+    for (int q = 0; q < 4; ++q) {
+      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
+      b_re[row * SLD + col] = accr[q];
+      b_im[row * SLD + col] = acci[q];
+      accr[q] = 0.0;
+      acci[q] = 0.0;
+    }
+#pragma unroll
+  for (int u = 0; u < BJ2 * BJ2 / kSolveThreads; ++u) {
+    const int idx = t + kSolveThreads * u;
+    a_re[(idx / BJ2) * SLD + idx % BJ2] = vp[u].re;
+    a_im[(idx / BJ2) * SLD + idx % BJ2] = vp[u].im;
+  }
+  __syncthreads();
+  if (t < 256) {
+    mm32(a_re, a_im, b_re, b_im, true, accr, acci);  // Y = V_P^H X
+    for (int q = 0; q < 4; ++q) {
+      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
+      const int gr = pair_index(P, row, step, nb), gc = pair_index(Q, col, step, nb);
+      Gd[(size_t)gr * mp + gc] = z64{accr[q], acci[q]};
+      if (P != Q) Gd[(size_t)gc * mp + gr] = z64{accr[q], -acci[q]};
+    }
+  }
+}
+
+constexpr int HLD = 17;  // leading dimension of the half-width (32 x 16) planes of rebuild_pair
+constexpr int kRebuildLds = 6 * BJ2 * SLD + 4 * BJ2 * HLD;  // doubles of scratch rebuild_pair uses
+
+// The 32x32 sub-problem of blocks (I, J) after the previous round's update, rebuilt from the
+// matrix before that update (Gs) and that round's rotations (V, flags pf, outer step ps) with
+// the very products the previous round's tile updates make: with P and Q the previous pairs of
+// I and J (offsets oI and oJ in them), the diagonal blocks are quadrants of V_P^H Gs_PP V_P and
+// V_Q^H Gs_QQ V_Q and the off-diagonal block one of the (min, max) tile, mirrored as that tile's
+// update mirrors it.  Only the quadrants needed are formed, each in the order of the whole-tile
+// product (mmq), so the block equals what the update writes.  Writes planes (hr, hi) (leading
+// dimension JLD), which may alias the scratch sc (kRebuildLds doubles); kSolveThreads threads.
+__device__ void rebuild_pair(int I, int J, const z64* __restrict__ Gs, int mp, int nb, int ps,
+                             const z64* __restrict__ V, const int* __restrict__ pf, double* __restrict__ sc,
+                             double* __restrict__ hr, double* __restrict__ hi) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int P, oI, Q, oJ;
+  block_home(I, ps, nb, P, oI);
+  block_home(J, ps, nb, Q, oJ);
+  const int fP = pf[P], fQ = pf[Q];
+  // tile u: rows of pair A[u], columns of pair B[u], quadrant (qr[u], qc[u]) of its update
+  const bool sw = P > Q;
+  const int A[3] = {P, sw ? Q : P, Q}, B[3] = {P, sw ? P : Q, Q};
+  const int qr[3] = {oI, sw ? oJ : oI, oJ}, qc[3] = {oI, sw ? oI : oJ, oJ};
+  const bool fA[3] = {fP != 0, sw ? fQ != 0 : fP != 0, fQ != 0}, fB[3] = {fP != 0, sw ? fP != 0 : fQ != 0, fQ != 0};
+  // scratch: tile u transposed (tr[u][kk][row], ld SLD), then the half V planes: columns oI..oI+15
+  // of V_P (vh[0]) and oJ..oJ+15 of V_Q (vh[1]), vh[kk][c] with ld HLD
+  double* tr_re[3] = {sc, sc + 2 * BJ2 * SLD, sc + 4 * BJ2 * SLD};
+  double* tr_im[3] = {sc + BJ2 * SLD, sc + 3 * BJ2 * SLD, sc + 5 * BJ2 * SLD};
+  double* vh_re[2] = {sc + 6 * BJ2 * SLD, sc + 6 * BJ2 * SLD + 2 * BJ2 * HLD};
+  double* vh_im[2] = {sc + 6 * BJ2 * SLD + BJ2 * HLD, sc + 6 * BJ2 * SLD + 3 * BJ2 * HLD};
+  // every load of the staging is issued before the first store (one memory latency, not eight)
+  z64 gv[6], vv[2];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const int u = i >> 1, e = t + (i & 1) * kSolveThreads, row = e / BJ2, kk = e % BJ2;
+    int a0, a1, b0, b1;  // blocks of pairs A[u] and B[u] (uniform)
+    rr_pair(A[u], ps, nb, a0, a1);
+    rr_pair(B[u], ps, nb, b0, b1);
+    const int gr = row < BJ ? a0 * BJ + row : a1 * BJ + row - BJ;
+    const int gc = kk < BJ ? b0 * BJ + kk : b1 * BJ + kk - BJ;
+    gv[i] = Gs[(size_t)gr * mp + gc];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = t / BJ, c = t % BJ, pr = h ? Q : P, off = h ? oJ : oI;
+    const bool f = h ? fQ : fP;
+    vv[h] = f ? V[(size_t)pr * BJ2 * BJ2 + r * BJ2 + off + c] : ((r == off + c) ? z64{1.0, 0.0} : z64{0.0, 0.0});
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const int u = i >> 1, e = t + (i & 1) * kSolveThreads, row = e / BJ2, kk = e % BJ2;
+    tr_re[u][kk * SLD + row] = gv[i].re;
+    tr_im[u][kk * SLD + row] = gv[i].im;
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = t / BJ, c = t % BJ;
+    vh_re[h][r * HLD + c] = vv[h].re;
+    vh_im[h][r * HLD + c] = vv[h].im;
+  }
+  __syncthreads();
+  // X = T V_B restricted to columns qc: waves 0..5 (tile w / 2, rows (w % 2) * 16)
+  const int xu = w >> 1, xr = (w & 1) * BJ;
+  const bool xrun = w < 6 && (fA[xu] || fB[xu]);
+  d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+  if (xrun) {
+    const int hb = (xu == 1) ? (sw ? 0 : 1) : (xu == 0 ? 0 : 1);  // half plane of V_B[u]
+    mmq(tr_re[xu], tr_im[xu], SLD, xr, vh_re[hb], vh_im[hb], HLD, 0, false, accr, acci);
+  }
+  __syncthreads();
+  if (xrun)  // X quadrant over the tile's own scratch: x[row][c], ld HLD
+    for (int q = 0; q < 4; ++q) {
+      const int row = xr + mfma_row_f64(lane, q), col = lane & 15;
+      tr_re[xu][row * HLD + col] = accr[q];
+      tr_im[xu][row * HLD + col] = acci[q];
+      accr[q] = 0.0;
+      acci[q] = 0.0;
+    }
+  __syncthreads();
+  // Y quadrant of tile w (waves 0..2): V_A^H X, or the quadrant of Gs itself when neither pair
+  // rotated (waves 3..5 read it)
+  double yr[4], yi[4];
+  if (w < 3) {
+    const int u = w;
+    if (fA[u] || fB[u]) {
+      const int ha = (u == 1) ? (sw ? 1 : 0) : (u == 0 ? 0 : 1);  // half plane of V_A[u]
+      mmq(vh_re[ha], vh_im[ha], HLD, 0, tr_re[u], tr_im[u], HLD, 0, true, accr, acci);
+      for (int q = 0; q < 4; ++q) {
+        yr[q] = accr[q];
+        yi[q] = acci[q];
+      }
+    }
+  } else if (w < 6) {
+    const int u = w - 3;
+    if (!(fA[u] || fB[u]))
+      for (int q = 0; q < 4; ++q) {  // element (row, col) of the quadrant, as the MFMA layout
+        const int row = mfma_row_f64(lane, q), col = lane & 15;
+        yr[q] = tr_re[u][(qc[u] + col) * SLD + qr[u] + row];
+        yi[q] = tr_im[u][(qc[u] + col) * SLD + qr[u] + row];
+      }
+  }
+  __syncthreads();
+  // place the quadrants: tile 0 -> (I, I), tile 2 -> (J, J), tile 1 -> (I, J) and its mirror
+  const int u = (w < 3) ? w : w - 3;
+  const bool mine = (w < 3) ? (fA[u] || fB[u]) : (w < 6 && !(fA[u] || fB[u]));
+  if (mine)
+    for (int q = 0; q < 4; ++q) {
+      const int row = mfma_row_f64(lane, q), col = lane & 15;
+      if (u == 0) {
+        hr[row * JLD + col] = yr[q];
+        hi[row * JLD + col] = yi[q];
+      } else if (u == 2) {
+        hr[(BJ + row) * JLD + BJ + col] = yr[q];
+        hi[(BJ + row) * JLD + BJ + col] = yi[q];
+      } else if (!sw) {  // rows of I, columns of J; mirror conjugated
+        hr[row * JLD + BJ + col] = yr[q];
+        hi[row * JLD + BJ + col] = yi[q];
+        hr[(BJ + col) * JLD + row] = yr[q];
+        hi[(BJ + col) * JLD + row] = -yi[q];
+      } else {  // the (Q, P) tile: rows of J, columns of I; mirror conjugated
+        hr[(BJ + row) * JLD + col] = yr[q];
+        hi[(BJ + row) * JLD + col] = yi[q];
+        hr[col * JLD + BJ + row] = yr[q];
+        hi[col * JLD + BJ + row] = -yi[q];
+      }
+    }
+}
+
 // Solve step of a round: pair k of outer step `step` solves its 32x32 sub-problem (blocks I, J)
 // and writes the accumulated rotation to V + k*32*32 (row-major) with a rotated flag.  The first
 // step of an outer sweep runs a full round-robin sweep over the 32 indices (covering the pairs
 // inside each block); later steps rotate only the 16 x 16 inter-block pairs.  Over one outer
-// sweep every index pair is visited once.  LDS: six 32 x JLD planes.
-__device__ void solve_pair(int k, const z64* __restrict__ Gp, int mp, int nb, int step, double thr, double tol,
+// sweep every index pair is visited once.  With ps < 0 the sub-problem is read from Gs; otherwise
+// Gs is the matrix before the previous round's update (outer step ps, rotations Vp, flags pfp)
+// and the sub-problem is rebuilt from it (rebuild_pair), the update itself running beside this
+// solve.  LDS: six 32 x JLD planes (the rebuild's scratch aliases them).
+__device__ void solve_pair(int k, const z64* __restrict__ Gs, int mp, int nb, int step, int ps,
+                           const z64* __restrict__ Vp, const int* __restrict__ pfp, double thr, double tol,
                            double skip, int rel, double floor2, z64* __restrict__ Vout, int* __restrict__ pair_flag,
                            int* __restrict__ any_flag, double* __restrict__ h0r, double* __restrict__ h0i,
                            double* __restrict__ h1r, double* __restrict__ h1i, double* __restrict__ vr,
@@ -672,16 +989,24 @@ __device__ void solve_pair(int k, const z64* __restrict__ Gp, int mp, int nb, in
   }
   if (full) build_rr_table(tab, BJ2);
   const JacobiArgs ja{thr, tol, skip, rel, floor2};
-  for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
-    const int i = idx / BJ2, j = idx % BJ2;
-    const int gi = (i < BJ ? I * BJ + i : J * BJ + (i - BJ));
-    const int gj = (j < BJ ? I * BJ + j : J * BJ + (j - BJ));
-    const z64 v = Gp[(size_t)gi * mp + gj];
-    h0r[i * JLD + j] = v.re;
-    h0i[i * JLD + j] = v.im;
-    vr[i * JLD + j] = (i == j) ? 1.0 : 0.0;
-    vi[i * JLD + j] = 0.0;
+  if (ps < 0) {
+    for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+      const int i = idx / BJ2, j = idx % BJ2;
+      const int gi = (i < BJ ? I * BJ + i : J * BJ + (i - BJ));
+      const int gj = (j < BJ ? I * BJ + j : J * BJ + (j - BJ));
+      const z64 v = Gs[(size_t)gi * mp + gj];
+      h0r[i * JLD + j] = v.re;
+      h0i[i * JLD + j] = v.im;
+    }
+  } else {
+    rebuild_pair(I, J, Gs, mp, nb, ps, Vp, pfp, h0r, h0r, h0i);
   }
+  if (full)
+    for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
+      const int i = idx / BJ2, j = idx % BJ2;
+      vr[i * JLD + j] = (i == j) ? 1.0 : 0.0;
+      vi[i * JLD + j] = 0.0;
+    }
   __syncthreads();
   for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
     const int i = idx / BJ2, j = idx % BJ2;
@@ -710,168 +1035,35 @@ __device__ void solve_pair(int k, const z64* __restrict__ Gp, int mp, int nb, in
   }
 }
 
-// 32x32x32 complex product on four waves (one 16x16 quadrant each): acc += A * B where A is
-// read as a[kk][row] (planes re/im, ld SLD) and B as b[kk][col]; conja conjugates A.
-__device__ __forceinline__ void mm32(const double* ar_, const double* ai_, const double* br_, const double* bi_,
-                                     bool conja, d4& accr, d4& acci) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
-#pragma unroll
-  for (int kk = 0; kk < BJ2; kk += 4) {
-    const int ka = kk + (lane >> 4);
-    const double ar = ar_[ka * SLD + wr + (lane & 15)];
-    const double ai = conja ? -ai_[ka * SLD + wr + (lane & 15)] : ai_[ka * SLD + wr + (lane & 15)];
-    const double br = br_[ka * SLD + wc + (lane & 15)];
-    const double bi = bi_[ka * SLD + wc + (lane & 15)];
-    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, accr, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, acci, 0, 0, 0);
-  }
-}
-
-__device__ __forceinline__ int pair_index(int P, int i, int step, int nb) {
-  int I, J;
-  rr_pair(P, step, nb, I, J);
-  return i < BJ ? I * BJ + i : J * BJ + (i - BJ);
-}
-
-// One 32x32 row tile (R, Q) of U <- U V_Q with 512 threads: all threads stage the operands, the
-// first four waves multiply (planes re/im in a_*/b_*, 32 x SLD each).
-__device__ void u_tile(z64* __restrict__ Up, int mp, int nb, int step, const z64* __restrict__ V,
-                       const int* __restrict__ pair_flag, int tile, double* __restrict__ a_re,
-                       double* __restrict__ a_im, double* __restrict__ b_re, double* __restrict__ b_im) {
-  const int half = nb / 2;
-  const int R = tile / half, Q = tile % half;
-  if (!pair_flag[Q]) return;  // uniform over the block
-  const int t = threadIdx.x, nt = blockDim.x;
-  const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
-  for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
-    const int row = idx / BJ2, kk = idx % BJ2;
-    const z64 v = Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, kk, step, nb)];
-    a_re[kk * SLD + row] = v.re;
-    a_im[kk * SLD + row] = v.im;
-    const z64 q = VQ[idx];
-    b_re[row * SLD + kk] = q.re;
-    b_im[row * SLD + kk] = q.im;
-  }
-  __syncthreads();
-  if (t < 256) {
-    const int lane = t & 63, w = t >> 6;
-    const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
-    d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-    mm32(a_re, a_im, b_re, b_im, false, accr, acci);
-    for (int q = 0; q < 4; ++q) {
-      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
-      Up[(size_t)(R * BJ2 + row) * mp + pair_index(Q, col, step, nb)] = z64{accr[q], acci[q]};
-    }
-  }
-}
-
-// One 32x32 tile (P, Q), P <= Q, of G <- V_P^H G V_Q with 512 threads (all stage the
-// operands, the first four waves multiply); the (Q, P) tile is written as the conjugate
-// transpose.  A pair that did not rotate contributes the identity; a tile whose two pairs both
-// did not rotate is left as it is.
-__device__ void g_tile(z64* __restrict__ Gp, int mp, int nb, int step, const z64* __restrict__ V,
-                       const int* __restrict__ pair_flag, int tile, double* __restrict__ a_re,
-                       double* __restrict__ a_im, double* __restrict__ b_re, double* __restrict__ b_im) {
-  const int half = nb / 2;
-  int P = 0, rem = tile;
-  while (rem >= half - P) {
-    rem -= half - P;
-    ++P;
-  }
-  const int Q = P + rem;
-  const int fP = pair_flag[P], fQ = pair_flag[Q];
-  if (!fP && !fQ) return;  // uniform over the block
-  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, w = t >> 6;
-  const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
-  const z64* VP = V + (size_t)P * BJ2 * BJ2;
-  const z64* VQ = V + (size_t)Q * BJ2 * BJ2;
-  // V_P is needed after the first product: fetch it into registers now
-  z64 vp[BJ2 * BJ2 / kSolveThreads];
-#pragma unroll
-  for (int u = 0; u < BJ2 * BJ2 / kSolveThreads; ++u) {
-    const int idx = t + kSolveThreads * u;
-    const int r = idx / BJ2, c = idx % BJ2;
-    vp[u] = fP ? VP[idx] : ((r == c) ? z64{1.0, 0.0} : z64{0.0, 0.0});
-  }
-  // a[kk][row] = T[row][kk] = G[rows(P)[row], cols(Q)[kk]];  b = V_Q (or the identity)
-  for (int idx = t; idx < BJ2 * BJ2; idx += nt) {
-    const int row = idx / BJ2, kk = idx % BJ2;
-    const z64 v = Gp[(size_t)pair_index(P, row, step, nb) * mp + pair_index(Q, kk, step, nb)];
-    a_re[kk * SLD + row] = v.re;
-    a_im[kk * SLD + row] = v.im;
-    const z64 q = fQ ? VQ[idx] : ((row == kk) ? z64{1.0, 0.0} : z64{0.0, 0.0});
-    b_re[row * SLD + kk] = q.re;
-    b_im[row * SLD + kk] = q.im;
-  }
-  __syncthreads();
-  d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-  if (t < 256) mm32(a_re, a_im, b_re, b_im, false, accr, acci);  // X = T V_Q
-  __syncthreads();
-  if (t < 256)
-    for (int q = 0; q < 4; ++q) {
-      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
-      b_re[row * SLD + col] = accr[q];
-      b_im[row * SLD + col] = acci[q];
-      accr[q] = 0.0;
-      acci[q] = 0.0;
-    }
-#pragma unroll
-  for (int u = 0; u < BJ2 * BJ2 / kSolveThreads; ++u) {
-    const int idx = t + kSolveThreads * u;
-    a_re[(idx / BJ2) * SLD + idx % BJ2] = vp[u].re;
-    a_im[(idx / BJ2) * SLD + idx % BJ2] = vp[u].im;
-  }
-  __syncthreads();
-  if (t < 256) {
-    mm32(a_re, a_im, b_re, b_im, true, accr, acci);  // Y = V_P^H X
-    for (int q = 0; q < 4; ++q) {
-      const int row = wr + mfma_row_f64(lane, q), col = wc + (lane & 15);
-      const int gr = pair_index(P, row, step, nb), gc = pair_index(Q, col, step, nb);
-      Gp[(size_t)gr * mp + gc] = z64{accr[q], acci[q]};
-      if (P != Q) Gp[(size_t)gc * mp + gr] = z64{accr[q], -acci[q]};
-    }
-  }
-}
-
-// Kernel B of a round: tile blockIdx.x + tile0 of the round's updates, the G tiles (P, Q),
-// P <= Q, first, then the row tiles of the eigenvector accumulator; 512 threads.
-__global__ __launch_bounds__(512) void k_jblock_apply(z64* __restrict__ Gp, z64* __restrict__ Up, int mp, int nb,
-                                                      int step, const z64* __restrict__ V,
-                                                      const int* __restrict__ pair_flag, int tile0) {
-  __shared__ double a_re[BJ2 * SLD], a_im[BJ2 * SLD], b_re[BJ2 * SLD], b_im[BJ2 * SLD];
-  const int half = nb / 2, ngt = half * (half + 1) / 2;
-  const int tile = blockIdx.x + tile0;
-  if (tile < ngt)
-    g_tile(Gp, mp, nb, step, V, pair_flag, tile, a_re, a_im, b_re, b_im);
-  else
-    u_tile(Up, mp, nb, step, V, pair_flag, tile - ngt, a_re, a_im, b_re, b_im);
-}
-
-// Kernel A of a round: blocks 0..half-1 solve the sub-problems of outer step `step` (rotations
-// to Vout, flags to pair_flag); when ustep >= 0 the remaining blocks apply the previous round's
-// rotations (Vprev, flags pflag_prev, its outer step ustep) to the eigenvector accumulator, one
-// row tile each.  The accumulator is not read by the solve or by the G update, so for large m
-// its update for round r runs beside round r+1's latency-bound solve on the otherwise idle CUs;
-// the rotation and flag buffers alternate between rounds.
-__global__ __launch_bounds__(512) void k_jblock_solve(const z64* __restrict__ Gp, z64* __restrict__ Up, int mp, int nb,
-                                                      int step, double thr, double tol, double skip, int rel,
-                                                      double floor2, z64* __restrict__ Vout, int* __restrict__ pair_flag,
-                                                      int* __restrict__ any_flag, int ustep,
-                                                      const z64* __restrict__ Vprev,
-                                                      const int* __restrict__ pflag_prev) {
-  constexpr int PL = BJ2 * JLD;  // the row tiles of u_tile (32 x SLD) fit in the first four planes
-  __shared__ double h0r[PL], h0i[PL], h1r[PL], h1i[PL], vr[PL], vi[PL];
+// One round of the block Jacobi sweep in one launch.  Blocks 0..half-1 (when step >= 0) solve the
+// sub-problems of outer step `step` (rotations to Vout, flags to pair_flag, any rotation to
+// *any_flag); when ps >= 0 the previous round (outer step ps, rotations Vp, flags pfp) is applied
+// beside them: the next half(half+1)/2 blocks form the tiles of Gd = V^H Gs V, the remaining
+// (mp/32) half blocks the row tiles of U <- U V.  The solves rebuild their sub-problems from Gs,
+// so no block waits for another; Gs and Gd alternate between rounds.  512 threads.
+__global__ __launch_bounds__(512) void k_jround(const z64* __restrict__ Gs, z64* __restrict__ Gd,
+                                                z64* __restrict__ Up, int mp, int nb, int step, int ps, double thr,
+                                                double tol, double skip, int rel, double floor2,
+                                                z64* __restrict__ Vout, int* __restrict__ pair_flag,
+                                                int* __restrict__ any_flag, const z64* __restrict__ Vp,
+                                                const int* __restrict__ pfp) {
+  constexpr int PL = BJ2 * JLD;
+  static_assert(6 * PL >= kRebuildLds, "the rebuild's scratch fits in the solve's planes");
+  __shared__ double pool[6 * PL];
   __shared__ unsigned char tab[31 * 32];
   __shared__ int any, need;
-  const int half = nb / 2;
-  if ((int)blockIdx.x < half)
-    solve_pair(blockIdx.x, Gp, mp, nb, step, thr, tol, skip, rel, floor2, Vout, pair_flag, any_flag, h0r, h0i, h1r, h1i,
-               vr, vi, tab, any, need);
-  else if (ustep >= 0)
-    u_tile(Up, mp, nb, ustep, Vprev, pflag_prev, blockIdx.x - half, h0r, h0i, h1r, h1i);
+  const int half = nb / 2, nsolve = step >= 0 ? half : 0, ngt = half * (half + 1) / 2;
+  int b = blockIdx.x;
+  if (b < nsolve) {
+    solve_pair(b, Gs, mp, nb, step, ps, Vp, pfp, thr, tol, skip, rel, floor2, Vout, pair_flag, any_flag, pool,
+               pool + PL, pool + 2 * PL, pool + 3 * PL, pool + 4 * PL, pool + 5 * PL, tab, any, need);
+    return;
+  }
+  b -= nsolve;
+  if (b < ngt)
+    g_tile(Gs, Gd, mp, nb, ps, Vp, pfp, b, pool, pool + BJ2 * SLD, pool + 2 * BJ2 * SLD, pool + 3 * BJ2 * SLD);
+  else
+    u_tile(Up, mp, nb, ps, Vp, pfp, b - ngt, pool, pool + BJ2 * SLD, pool + 2 * BJ2 * SLD, pool + 3 * BJ2 * SLD);
 }
 
 __global__ void k_pad_copy(const z64* __restrict__ G, int m, int ldg, z64* __restrict__ Gp, int mp,
@@ -1166,6 +1358,7 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   GC_CHECK(mp <= w.m_pad, GCAMPS_ECAPACITY, "eigensolver workspace too small");
   z64* Gp = w.G;
   z64* Up = w.G + (size_t)w.m_pad * w.m_pad;
+  z64* Gp1 = w.G + 2 * (size_t)w.m_pad * w.m_pad;
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks_for((size_t)mp * mp, 256)), dim3(256), 0, s, G, m, ldg, Gp, mp, Up);
   GC_LAUNCH_CHECK();
   double* d_trace = reinterpret_cast<double*>(w.flags + 512);
@@ -1197,23 +1390,20 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   GC_CHECK(half <= 128, GCAMPS_ECAPACITY, "eigensolver: matrix side exceeds 4096");
   auto vbuf = [&](long r) { return w.V + (size_t)(r & 1) * half * BJ2 * BJ2; };
   auto fbuf = [&](long r) { return w.flags + 1 + (r & 1) * 128; };
+  // the matrix after round r - 1's update lives in gbuf(r): round r (r >= 1) solves from gbuf(r - 1)
+  // and the previous round's rotations while it writes gbuf(r)
+  auto gbuf = [&](long r) { return (r & 1) ? Gp1 : Gp; };
   const int gtiles = half * (half + 1) / 2, utiles = (mp / BJ2) * half;
-  // Deferring round r's U update into round r + 1's solve launch pays once the apply launch is
-  // throughput-bound: measured 11% faster per decomposition at m = 1536, 3% slower at m = 768
-  // (there the apply is latency-bound and the U tiles only contend with the solve).
-  const bool defer = mp > 1024;
-  long round = 0;  // rounds launched so far; with defer, round - 1 still owes its U update
+  long round = 0;  // rounds launched so far
   int prev_step = -1;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     GC_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
     for (int step = 0; step < nb - 1; ++step, ++round) {
-      const bool owe = defer && round > 0;
-      hipLaunchKernelGGL(k_jblock_solve, dim3(half + (owe ? utiles : 0)), dim3(kSolveThreads), 0, s, Gp, Up, mp, nb,
-                         step, thr, tol, skipv, rel, floor2, vbuf(round), fbuf(round), w.flags, owe ? prev_step : -1,
-                         owe ? vbuf(round - 1) : nullptr, owe ? fbuf(round - 1) : nullptr);
-      GC_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_jblock_apply, dim3(defer ? gtiles : gtiles + utiles), dim3(kSolveThreads), 0, s, Gp, Up,
-                         mp, nb, step, vbuf(round), fbuf(round), 0);
+      const bool upd = round > 0;
+      hipLaunchKernelGGL(k_jround, dim3(half + (upd ? gtiles + utiles : 0)), dim3(kSolveThreads), 0, s,
+                         upd ? gbuf(round - 1) : Gp, gbuf(round), Up, mp, nb, step, upd ? prev_step : -1, thr, tol,
+                         skipv, rel, floor2, vbuf(round), fbuf(round), w.flags, upd ? vbuf(round - 1) : nullptr,
+                         upd ? fbuf(round - 1) : nullptr);
       GC_LAUNCH_CHECK();
       prev_step = step;
     }
@@ -1228,12 +1418,13 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
       break;
     }
   }
-  if (defer && round > 0) {  // the last round's U update
-    hipLaunchKernelGGL(k_jblock_apply, dim3(utiles), dim3(kSolveThreads), 0, s, Gp, Up, mp, nb, prev_step,
-                       vbuf(round - 1), fbuf(round - 1), gtiles);
-    GC_LAUNCH_CHECK();
-  }
-  hipLaunchKernelGGL(k_unpad, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gp, Up, m, mp, U, ldu, lam);
+  // the last round's update: G into gbuf(round), U in place
+  hipLaunchKernelGGL(k_jround, dim3(gtiles + utiles), dim3(kSolveThreads), 0, s, gbuf(round - 1), gbuf(round), Up, mp,
+                     nb, -1, prev_step, thr, tol, skipv, rel, floor2, nullptr, nullptr, w.flags, vbuf(round - 1),
+                     fbuf(round - 1));
+  GC_LAUNCH_CHECK();
+  const z64* Gf = gbuf(round);
+  hipLaunchKernelGGL(k_unpad, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gf, Up, m, mp, U, ldu, lam);
   GC_LAUNCH_CHECK();
   GC_CHECK(conv, GCAMPS_ENUMERIC,
            std::string("block Jacobi eigensolver did not converge (m = ") + std::to_string(m) +
