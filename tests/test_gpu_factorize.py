@@ -1,8 +1,8 @@
 """The split's factorisation on its own (gcamps_factorize: Gram on MFMA, block-Jacobi eigensolver,
 truncation rule, emit) against LAPACK singular values and the oracle's truncation rule, from
 1 x 7 up to the library's maximum matrix side, 4096 (a ctx with chi_max = 2048 and d = 2): there
-the eigensolver runs 128 sub-problems per round and defers each round's eigenvector update into
-the next solve launch.
+the eigensolver runs 128 sub-problems per round, each rebuilt from the matrix before the previous
+round's update while that update runs in the same launch.
 
 Bars.  With sigma_0 the largest singular value:
 - kept rank equals the oracle's rule on the LAPACK values (the cases are built with no value
