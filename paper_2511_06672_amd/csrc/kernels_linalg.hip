@@ -1042,11 +1042,11 @@ __device__ void solve_pair(int k, const z64* __restrict__ Gs, int mp, int nb, in
 // (mp/32) half blocks the row tiles of U <- U V.  The solves rebuild their sub-problems from Gs,
 // so no block waits for another; Gs and Gd alternate between rounds.  512 threads.
 __global__ __launch_bounds__(512) void k_jround(const z64* __restrict__ Gs, z64* __restrict__ Gd,
-                                                z64* __restrict__ Up, int mp, int nb, int step, int ps, double thr,
-                                                double tol, double skip, int rel, double floor2,
-                                                z64* __restrict__ Vout, int* __restrict__ pair_flag,
-                                                int* __restrict__ any_flag, const z64* __restrict__ Vp,
-                                                const int* __restrict__ pfp) {
+                                                z64* __restrict__ Up, int mp, int nb, int step, int ps,
+                                                const double* __restrict__ trace, double tol, double skip_rel,
+                                                int rel, double floor_rel, z64* __restrict__ Vout,
+                                                int* __restrict__ pair_flag, int* __restrict__ any_flag,
+                                                const z64* __restrict__ Vp, const int* __restrict__ pfp) {
   constexpr int PL = BJ2 * JLD;
   static_assert(6 * PL >= kRebuildLds, "the rebuild's scratch fits in the solve's planes");
   // Sized past half of a CU's 160 KB so that one block holds a CU: a solve then never shares its
@@ -1060,6 +1060,9 @@ __global__ __launch_bounds__(512) void k_jround(const z64* __restrict__ Gs, z64*
   const int half = nb / 2, nsolve = step >= 0 ? half : 0, ngt = half * (half + 1) / 2;
   int b = blockIdx.x;
   if (b < nsolve) {
+    // thresholds from the trace on the device (read by no host sync)
+    const double tr = *trace;
+    const double thr = tol * tr, skip = skip_rel * tr, floor2 = (floor_rel * tr) * (floor_rel * tr);
     solve_pair(b, Gs, mp, nb, step, ps, Vp, pfp, thr, tol, skip, rel, floor2, Vout, pair_flag, any_flag, pool,
                pool + PL, pool + 2 * PL, pool + 3 * PL, pool + 4 * PL, pool + 5 * PL, tab, any, need);
     return;
@@ -1374,19 +1377,20 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
                        skip, rel, floor_rel, reinterpret_cast<int*>(d_trace + 1));
     GC_LAUNCH_CHECK();
   }
-  double tr_flag[2] = {0.0, 0.0};  // the trace and, after it, the pre-check flag
-  GC_HIP(hipMemcpyAsync(tr_flag, d_trace, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  GC_HIP(hipStreamSynchronize(s));
-  const double trace = tr_flag[0];
-  int pre_hit = 1;
-  std::memcpy(&pre_hit, &tr_flag[1], sizeof(int));
-  if (precheck && !pre_hit) {  // nothing to rotate: U = I (set by k_pad_copy), lam = diag(G)
-    hipLaunchKernelGGL(k_unpad, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gp, Up, m, mp, U, ldu, lam);
-    GC_LAUNCH_CHECK();
-    if (host_sweeps) *host_sweeps = 0;
-    return;
+  if (precheck) {  // the pre-check flag sits after the trace; the rounds read the trace themselves
+    double tr_flag[2] = {0.0, 0.0};
+    GC_HIP(hipMemcpyAsync(tr_flag, d_trace, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    GC_HIP(hipStreamSynchronize(s));
+    int pre_hit = 1;
+    std::memcpy(&pre_hit, &tr_flag[1], sizeof(int));
+    if (!pre_hit) {  // nothing to rotate: U = I (set by k_pad_copy), lam = diag(G)
+      hipLaunchKernelGGL(k_unpad, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gp, Up, m, mp, U, ldu,
+                         lam);
+      GC_LAUNCH_CHECK();
+      if (host_sweeps) *host_sweeps = 0;
+      return;
+    }
   }
-  const double thr = tol * trace, skipv = skip * trace, floor2 = (floor_rel * trace) * (floor_rel * trace);
   const int half = nb / 2;
   int sweeps = 0;
   bool conv = false;
@@ -1406,8 +1410,8 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
     for (int step = 0; step < nb - 1; ++step, ++round) {
       const bool upd = round > 0;
       hipLaunchKernelGGL(k_jround, dim3(half + (upd ? gtiles + utiles : 0)), dim3(kSolveThreads), 0, s,
-                         upd ? gbuf(round - 1) : Gp, gbuf(round), Up, mp, nb, step, upd ? prev_step : -1, thr, tol,
-                         skipv, rel, floor2, vbuf(round), fbuf(round), w.flags, upd ? vbuf(round - 1) : nullptr,
+                         upd ? gbuf(round - 1) : Gp, gbuf(round), Up, mp, nb, step, upd ? prev_step : -1, d_trace,
+                         tol, skip, rel, floor_rel, vbuf(round), fbuf(round), w.flags, upd ? vbuf(round - 1) : nullptr,
                          upd ? fbuf(round - 1) : nullptr);
       GC_LAUNCH_CHECK();
       prev_step = step;
@@ -1425,7 +1429,7 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   }
   // the last round's update: G into gbuf(round), U in place
   hipLaunchKernelGGL(k_jround, dim3(gtiles + utiles), dim3(kSolveThreads), 0, s, gbuf(round - 1), gbuf(round), Up, mp,
-                     nb, -1, prev_step, thr, tol, skipv, rel, floor2, nullptr, nullptr, w.flags, vbuf(round - 1),
+                     nb, -1, prev_step, d_trace, tol, skip, rel, floor_rel, nullptr, nullptr, w.flags, vbuf(round - 1),
                      fbuf(round - 1));
   GC_LAUNCH_CHECK();
   const z64* Gf = gbuf(round);
