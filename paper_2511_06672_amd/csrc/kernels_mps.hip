@@ -13,6 +13,7 @@
 #include <cfloat>
 
 #include "kernels.h"
+#include "tune.h"
 
 namespace gc {
 
@@ -302,10 +303,13 @@ __device__ __forceinline__ void tile_pair(int idx, int nt, int& I, int& J) {
   J = i + rem;
 }
 
-// Candidates per generator thread: kGenCands for chunks of at least kGenMinChunk candidates,
-// else one.  Lists whose length is only known on the device (the window re-score) take one too:
-// they are usually short, and a few candidates need every block they can get.
+// Candidates per generator thread: for chunks of at least kGenMinChunk candidates the tuner's
+// pick among kGenCpt per (precision, d, chi_l, chi_r) (kGenCands without tuning), else one.
+// Lists whose length is only known on the device (the window re-score) take one too: they are
+// usually short, and a few candidates need every block they can get.  The generated matrices
+// are the same for every choice.
 constexpr int kGenCands = 8, kGenMinChunk = 64;
+constexpr int kGenCpt[] = {1, 2, 4, 8};
 
 // Rotated two-site matrices N_c (m x k, row-major, leading dimension ldk >= k) for a chunk of
 // candidates.  One thread per (a, b) loads Theta(a, :, :, b) once and writes the d^2 entries
@@ -1098,6 +1102,15 @@ void launch_rotate_copy(hipStream_t s, int d, int chil, int chir, int c, const z
   GC_LAUNCH_CHECK();
 }
 
+// Candidates per generator thread for full-set chunks of `first` candidates: the tuner's pick per
+// (precision, d, chi_l, chi_r), timed on the first chunk (gen(c0, cnt, cpt) launches the generator).
+template <typename Gen>
+int gen_cpt(hipStream_t s, int prec, int d, int chil, int chir, const int* nlimit, int first, const Gen& gen) {
+  if (nlimit || first < kGenMinChunk) return kGenCands;  // such chunks take one candidate per thread
+  return tuned_choice(s, "gen_cpt", prec, d, chil, chir, kGenCpt, (int)(sizeof(kGenCpt) / sizeof(kGenCpt[0])),
+                      kGenCands, [&](int cpt) { gen(0, first, cpt); });
+}
+
 void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64* theta, const z64* q64, const c32* q32,
                   const int* list, int count, const int* nlimit, double* s2, double* partial, size_t partial_cap,
                   void* nbuf, size_t nbuf_bytes, hipEvent_t* evs, int evcap, int* evused, const z64* replica_tables) {
@@ -1132,12 +1145,8 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
     const int chunk = (int)std::min<size_t>((size_t)count, nbuf_bytes / (stride * sizeof(__bf16)));
     GC_CHECK(chunk >= 1, GCAMPS_ECAPACITY, "rotated-matrix buffer too small");
     __bf16* nb = reinterpret_cast<__bf16*>(nbuf);
-    for (int c0 = 0; c0 < count; c0 += chunk) {
-      const int cnt = std::min(chunk, count - c0);
-      const int cpt = (!nlimit && cnt >= kGenMinChunk) ? kGenCands : 1;
-      const dim3 gg(blocks_for((size_t)chil * chir, 256), (cnt + cpt - 1) / cpt),
-          gp((unsigned)ntp * ((cnt + 7) / 8) * 8);
-      const int ev = (evs && evused && 2 * (*evused) + 1 < evcap) ? 2 * (*evused) : -1;
+    auto gen = [&](int c0, int cnt, int cpt) {
+      const dim3 gg(blocks_for((size_t)chil * chir, 256), (cnt + cpt - 1) / cpt);
       if (d == 3)
         hipLaunchKernelGGL((k_gen_rotated_bf16<3>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
                            nlimit, nb, stride, ldk, cpt);
@@ -1147,6 +1156,15 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
       else
         hipLaunchKernelGGL((k_gen_rotated_bf16<0>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
                            nlimit, nb, stride, ldk, cpt);
+      GC_LAUNCH_CHECK();
+    };
+    const int cpt_full = gen_cpt(s, prec, d, chil, chir, nlimit, std::min(chunk, count), gen);
+    for (int c0 = 0; c0 < count; c0 += chunk) {
+      const int cnt = std::min(chunk, count - c0);
+      const int cpt = (!nlimit && cnt >= kGenMinChunk) ? cpt_full : 1;
+      const dim3 gp((unsigned)ntp * ((cnt + 7) / 8) * 8);
+      const int ev = (evs && evused && 2 * (*evused) + 1 < evcap) ? 2 * (*evused) : -1;
+      gen(c0, cnt, cpt);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
       hipLaunchKernelGGL(k_gram_purity_bf16, gp, dim3(256), 0, s, m, ldk, nb, stride, c0, cnt, nlimit, ntp, partial);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
@@ -1168,12 +1186,8 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
   const int chunk = (int)std::min<size_t>((size_t)count, nbuf_bytes / (stride * elem));
   GC_CHECK(chunk >= 1, GCAMPS_ECAPACITY, "rotated-matrix buffer too small");
 
-  for (int c0 = 0; c0 < count; c0 += chunk) {
-    const int cnt = std::min(chunk, count - c0);
-    const int cpt = (!nlimit && cnt >= kGenMinChunk) ? kGenCands : 1;
-    const dim3 gg(blocks_for((size_t)chil * chir, 256), (cnt + cpt - 1) / cpt),
-        gp((unsigned)ntp * ((cnt + 7) / 8) * 8);
-    const int ev = (evs && evused && 2 * (*evused) + 1 < evcap) ? 2 * (*evused) : -1;
+  auto gen = [&](int c0, int cnt, int cpt) {
+    const dim3 gg(blocks_for((size_t)chil * chir, 256), (cnt + cpt - 1) / cpt);
     if (prec == GCAMPS_SCORE_FP64) {
       z64* nb = reinterpret_cast<z64*>(nbuf);
       if (d == 3)
@@ -1185,10 +1199,6 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
       else
         hipLaunchKernelGGL((k_gen_rotated<double, 0>), gg, dim3(256), 0, s, d, chil, chir, theta, q64, list, c0, cnt,
                            nlimit, nb, stride, ldk, cpt);
-      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
-      hipLaunchKernelGGL((k_gram_purity<double, 2, 4>), gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
-                         partial);
-      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
     } else {
       c32* nb = reinterpret_cast<c32*>(nbuf);
       if (d == 3)
@@ -1200,6 +1210,24 @@ void launch_score(hipStream_t s, int prec, int d, int chil, int chir, const z64*
       else
         hipLaunchKernelGGL((k_gen_rotated<float, 0>), gg, dim3(256), 0, s, d, chil, chir, theta, q32, list, c0, cnt,
                            nlimit, nb, stride, ldk, cpt);
+    }
+    GC_LAUNCH_CHECK();
+  };
+  const int cpt_full = gen_cpt(s, prec, d, chil, chir, nlimit, std::min(chunk, count), gen);
+  for (int c0 = 0; c0 < count; c0 += chunk) {
+    const int cnt = std::min(chunk, count - c0);
+    const int cpt = (!nlimit && cnt >= kGenMinChunk) ? cpt_full : 1;
+    const dim3 gp((unsigned)ntp * ((cnt + 7) / 8) * 8);
+    const int ev = (evs && evused && 2 * (*evused) + 1 < evcap) ? 2 * (*evused) : -1;
+    gen(c0, cnt, cpt);
+    if (prec == GCAMPS_SCORE_FP64) {
+      z64* nb = reinterpret_cast<z64*>(nbuf);
+      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
+      hipLaunchKernelGGL((k_gram_purity<double, 2, 4>), gp, dim3(256), 0, s, m, k, nb, stride, c0, cnt, nlimit, ntp,
+                         partial);
+      if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
+    } else {
+      c32* nb = reinterpret_cast<c32*>(nbuf);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev], s));
       hipLaunchKernelGGL(k_gram_purity_dl, gp, dim3(512), 0, s, m, ldk, nb, stride, c0, cnt, nlimit, ntp, partial);
       if (ev >= 0) GC_HIP(hipEventRecord(evs[ev + 1], s));
