@@ -211,7 +211,10 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
     Layout lay = make_layout(*cfg);
     GC_CHECK(bytes >= lay.total, GCAMPS_EWORKSPACE, "workspace smaller than gcamps_workspace_bytes()");
     static std::once_flag attrs_once;
-    std::call_once(attrs_once, [] { rank_set_attributes(); });
+    std::call_once(attrs_once, [] {
+      rank_set_attributes();
+      linalg_set_attributes();
+    });
     int dev = 0;
     GC_HIP(hipGetDevice(&dev));
     void* sdev = scratch_address(dev);  // static scratch of gcamps_statevector_static on this GPU

@@ -120,6 +120,7 @@ void launch_cand_rank(hipStream_t s, int d, int chil, int chir, const z64* theta
 void launch_select_rank(hipStream_t s, int count, const int* rank, const double* s2, double tie_tol,
                         DevStatus* st);
 void rank_set_attributes();
+void linalg_set_attributes();  // the block-Jacobi rounds' dynamic LDS limit
 
 // ------------------------------------------------------------------ replica scoring (kernels_replica.hip)
 // Full-set scores through the replica tensor of Theta (d = 2, 3): the Gram F of Theta over its

@@ -1041,6 +1041,12 @@ __device__ void solve_pair(int k, const z64* __restrict__ Gs, int mp, int nb, in
 // beside them: the next half(half+1)/2 blocks form the tiles of Gd = V^H Gs V, the remaining
 // (mp/32) half blocks the row tiles of U <- U V.  The solves rebuild their sub-problems from Gs,
 // so no block waits for another; Gs and Gd alternate between rounds.  512 threads.
+// Launched with kJroundPad bytes of (unused) dynamic LDS, a block holds more than half of a CU's
+// 160 KB, so it holds the CU alone: a solve then never shares its SIMDs with tile updates (the
+// round's critical path), which queue on the other CUs.  That pays while the updates are few
+// (m = 768: 21.0 against 22.8 us per round) and costs once they dominate (m = 1024: 26.6
+// against 24.5 us; m = 2048: 89.9 against 59.8 us), where it is launched without the pad.
+constexpr int kJroundPad = 8192;
 __global__ __launch_bounds__(512) void k_jround(const z64* __restrict__ Gs, z64* __restrict__ Gd,
                                                 z64* __restrict__ Up, int mp, int nb, int step, int ps,
                                                 const double* __restrict__ trace, double tol, double skip_rel,
@@ -1049,13 +1055,9 @@ __global__ __launch_bounds__(512) void k_jround(const z64* __restrict__ Gs, z64*
                                                 const z64* __restrict__ Vp, const int* __restrict__ pfp) {
   constexpr int PL = BJ2 * JLD;
   static_assert(6 * PL >= kRebuildLds, "the rebuild's scratch fits in the solve's planes");
-  // Sized past half of a CU's 160 KB so that one block holds a CU: a solve then never shares its
-  // SIMDs with tile updates (the round's critical path), which queue on the other CUs instead
-  // (at m = 768: 21.0 against 22.8 us per round).
-  constexpr int kPool = 10240;
-  __shared__ double pool[kPool];
+  __shared__ double pool[6 * PL];
   __shared__ unsigned char tab[31 * 32];
-  static_assert(kPool >= 6 * PL && sizeof(pool) + sizeof(tab) > 80 * 1024, "pool holds the planes and half a CU's LDS");
+  static_assert(sizeof(pool) + sizeof(tab) + kJroundPad > 80 * 1024, "a padded block holds half a CU's LDS");
   __shared__ int any, need;
   const int half = nb / 2, nsolve = step >= 0 ? half : 0, ngt = half * (half + 1) / 2;
   int b = blockIdx.x;
@@ -1306,6 +1308,13 @@ inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / 
 }  // namespace
 
 // ===================================================================================== launchers
+void linalg_set_attributes() {
+  // the rounds' optional LDS pad is dynamic shared memory; static plus dynamic exceeds 64 KB
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_jround), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kJroundPad);
+  (void)hipGetLastError();
+}
+
 void launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, const z64* A, int lda, const z64* B,
                   int ldb, z64* C, int ldc, z64 alpha, int accumulate, int herm) {
   if (M <= 0 || N <= 0) return;
@@ -1403,13 +1412,15 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   // and the previous round's rotations while it writes gbuf(r)
   auto gbuf = [&](long r) { return (r & 1) ? Gp1 : Gp; };
   const int gtiles = half * (half + 1) / 2, utiles = (mp / BJ2) * half;
+  // a whole CU per block while the tile updates are few (see k_jround)
+  const size_t pad = mp <= 896 ? kJroundPad : 0;
   long round = 0;  // rounds launched so far
   int prev_step = -1;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     GC_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
     for (int step = 0; step < nb - 1; ++step, ++round) {
       const bool upd = round > 0;
-      hipLaunchKernelGGL(k_jround, dim3(half + (upd ? gtiles + utiles : 0)), dim3(kSolveThreads), 0, s,
+      hipLaunchKernelGGL(k_jround, dim3(half + (upd ? gtiles + utiles : 0)), dim3(kSolveThreads), pad, s,
                          upd ? gbuf(round - 1) : Gp, gbuf(round), Up, mp, nb, step, upd ? prev_step : -1, d_trace,
                          tol, skip, rel, floor_rel, vbuf(round), fbuf(round), w.flags, upd ? vbuf(round - 1) : nullptr,
                          upd ? fbuf(round - 1) : nullptr);
@@ -1428,7 +1439,7 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
     }
   }
   // the last round's update: G into gbuf(round), U in place
-  hipLaunchKernelGGL(k_jround, dim3(gtiles + utiles), dim3(kSolveThreads), 0, s, gbuf(round - 1), gbuf(round), Up, mp,
+  hipLaunchKernelGGL(k_jround, dim3(gtiles + utiles), dim3(kSolveThreads), pad, s, gbuf(round - 1), gbuf(round), Up, mp,
                      nb, -1, prev_step, d_trace, tol, skip, rel, floor_rel, nullptr, nullptr, w.flags, vbuf(round - 1),
                      fbuf(round - 1));
   GC_LAUNCH_CHECK();
