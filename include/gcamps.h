@@ -27,6 +27,10 @@
  * - Site numbering starts at 0 (site 0 is the most significant digit of a
  *   computational-basis index).  Weyl phases are powers of tau = exp(i pi/d).
  * - Results are deterministic: identical inputs give bit-identical outputs.
+ * - Environment: GCAMPS_AUTOTUNE=0 turns off the launch tuner, which times a
+ *   few result-neutral launch parameters (candidates per thread of the scoring
+ *   generator) once per shape and process; GCAMPS_TUNE_FILE=path keeps its
+ *   picks in a JSON file across runs.  Neither changes any result.
  * - After GCAMPS_EDEVICE or GCAMPS_ENUMERIC the ctx is poisoned: only getters
  *   and gcamps_destroy may follow.  Other failed calls leave the state as it
  *   was.
