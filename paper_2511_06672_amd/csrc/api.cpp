@@ -276,6 +276,8 @@ int32_t gcamps_init(const gcamps_config* cfg, void* dev_workspace, size_t bytes,
     c->pcst = reinterpret_cast<PcState*>(w + lay.off_pcst);
     c->pinned_bytes = std::max<size_t>(1 << 20, (size_t)n * 2401 * 4 + 4096);
     GC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->pinned), c->pinned_bytes, hipHostMallocDefault));
+    GC_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->rb), kRbBytes, hipHostMallocDefault));
+    c->eig.host_rb = reinterpret_cast<double*>(c->rb + kRbEig);
     GC_HIP(hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming));
     GC_HIP(hipEventCreate(&c->ev0));
     GC_HIP(hipEventCreate(&c->ev1));

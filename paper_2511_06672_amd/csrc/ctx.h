@@ -122,6 +122,7 @@ struct gcamps_ctx {
   uint64_t cand_uid = 0;
   // pinned staging
   char* pinned = nullptr;
+  char* rb = nullptr;  // pinned read-back block (status, Cholesky state, eigensolver flags)
   size_t pinned_bytes = 0;
   hipEvent_t stage_ev = nullptr;
   bool stage_pending = false;
@@ -157,6 +158,7 @@ struct gcamps_ctx {
 
   ~gcamps_ctx() {
     if (pinned) (void)hipHostFree(pinned);
+    if (rb) (void)hipHostFree(rb);
     if (stage_ev) (void)hipEventDestroy(stage_ev);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -180,9 +182,13 @@ struct gcamps_ctx {
     GC_HIP(hipEventRecord(stage_ev, stream));
     stage_pending = true;
   }
-  void read_status(DevStatus& h) {
-    GC_HIP(hipMemcpyAsync(&h, st, sizeof(DevStatus), hipMemcpyDeviceToHost, stream));
+  static_assert(sizeof(DevStatus) <= kRbPcState && kRbPcState + sizeof(PcState) <= kRbEig &&
+                    kRbWeyl + sizeof(DevWeyl) <= kRbWeylErr && kRbWeylErr + sizeof(int) <= kRbBytes,
+                "read-back block layout");
+  void read_status(DevStatus& h) {  // through pinned memory: no staging copy
+    GC_HIP(hipMemcpyAsync(rb + kRbStatus, st, sizeof(DevStatus), hipMemcpyDeviceToHost, stream));
     GC_HIP(hipStreamSynchronize(stream));
+    std::memcpy(&h, rb + kRbStatus, sizeof(DevStatus));
   }
 
   int dim_l(int i) const { return chi[i]; }
@@ -223,8 +229,9 @@ struct gcamps_ctx {
       // its directions hold less than the cutoff even all together, and no eigenvalue moves by
       // more than the Gram's own rounding
       const double tol_rel = std::min(1e-14, cfg.cutoff / (2.0 * m));
-      PcState hs{};
-      const int r = pchol_reduce(stream, G, m, m, Z, m, tol_rel, m, sig, perm, pcst, &hs);
+      PcState* hsp = reinterpret_cast<PcState*>(rb + kRbPcState);
+      const int r = pchol_reduce(stream, G, m, m, Z, m, tol_rel, m, sig, perm, pcst, hsp);
+      const PcState hs = *hsp;
       if (hs.done && r >= 1) {
         // H = L^H L = Y lam Y^H with relative accuracy, so that the columns of L Y are
         // orthogonal to ~1e-14 of their norms even where lam is tiny (an absolute criterion
@@ -425,11 +432,13 @@ struct gcamps_ctx {
     for (int i = 0; i < 2 * n + 1; ++i) tg[i] = xzp[i];
     stage_upload(target, (2 * n + 1) * sizeof(int));
     launch_weyl_extract(stream, n, d, tx, tz, tp, target, weyl, derr);
+    GC_HIP(hipMemcpyAsync(rb + kRbWeyl, weyl, sizeof(DevWeyl), hipMemcpyDeviceToHost, stream));
+    GC_HIP(hipMemcpyAsync(rb + kRbWeylErr, derr, sizeof(int), hipMemcpyDeviceToHost, stream));
+    GC_HIP(hipStreamSynchronize(stream));
     DevWeyl P;
     int err = 0;
-    GC_HIP(hipMemcpyAsync(&P, weyl, sizeof(DevWeyl), hipMemcpyDeviceToHost, stream));
-    GC_HIP(hipMemcpyAsync(&err, derr, sizeof(int), hipMemcpyDeviceToHost, stream));
-    GC_HIP(hipStreamSynchronize(stream));
+    std::memcpy(&P, rb + kRbWeyl, sizeof(DevWeyl));
+    std::memcpy(&err, rb + kRbWeylErr, sizeof(int));
     GC_CHECK(err == 0, GCAMPS_ENUMERIC, "tableau decomposition failed");
     GateRec g;
     g.l = P.l;

@@ -32,7 +32,11 @@ struct EigWork {
   z64* V;      // block rotations
   int* flags;  // device flags
   int m_pad;
+  double* host_rb;  // pinned host read-back slots (2 doubles)
 };
+// Offsets in a context's pinned read-back block: device status, Cholesky state, eigensolver
+// slots, conjugated Weyl string and its error flag.
+constexpr size_t kRbStatus = 0, kRbPcState = 256, kRbEig = 512, kRbWeyl = 1024, kRbWeylErr = 2560, kRbBytes = 4096;
 // precheck: test every pair against the rotation criterion first and return U = I, lam =
 // diag(G) without a sweep when none qualifies (for matrices expected to be diagonal already,
 // e.g. a Rayleigh-Ritz step; the result equals what one sweep that rotates nothing leaves).

@@ -1387,7 +1387,8 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
     GC_LAUNCH_CHECK();
   }
   if (precheck) {  // the pre-check flag sits after the trace; the rounds read the trace themselves
-    double tr_flag[2] = {0.0, 0.0};
+    double local[2] = {0.0, 0.0};
+    double* tr_flag = w.host_rb ? w.host_rb : local;  // pinned when the context gives a slot
     GC_HIP(hipMemcpyAsync(tr_flag, d_trace, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
     int pre_hit = 1;
@@ -1430,9 +1431,11 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
     ++sweeps;
     // (A check after each sweep for pairs left to rotate, to skip the sweep that only confirms
     // convergence, costs as much here as that sweep: its rounds are cheap when nothing rotates.)
-    int any = 0;
-    GC_HIP(hipMemcpyAsync(&any, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    int local = 0;
+    int* hany = w.host_rb ? reinterpret_cast<int*>(w.host_rb) : &local;  // pinned when given
+    GC_HIP(hipMemcpyAsync(hany, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
+    const int any = *hany;
     if (!any) {
       conv = true;
       break;
