@@ -53,17 +53,20 @@ __global__ __launch_bounds__(256) void k_pchol_init(const z64* __restrict__ G, i
   }
 }
 
-// One panel of NB pivot steps; thread t owns rows t, t + 512, ..., t + (RPT - 1) 512.
+// One panel of NB pivot steps; thread t owns rows t, t + 512, ..., t + (RPT - 1) 512.  One
+// barrier per step: each wave posts its remaining trace, its pivot candidate and that row's
+// entries in the panel's earlier columns; every thread then combines the eight posts in the same
+// order.  The posting slots alternate between two sets by step parity, so a wave may post step
+// jj + 1 while a slower one still reads step jj.
 template <int RPT, int NB>
 __global__ __launch_bounds__(kPcThreads) void k_pchol_panel(const z64* __restrict__ G, int m, int ldg,
                                                             double* __restrict__ dvec, int* __restrict__ pv,
                                                             z64* __restrict__ L, int ldl, PcState* __restrict__ stt,
                                                             double tol_rel) {
-  __shared__ double w_sum[kPcThreads / 64], w_max[kPcThreads / 64];
-  __shared__ int w_idx[kPcThreads / 64];
-  __shared__ double b_sum, b_max;
-  __shared__ int b_idx;
-  __shared__ z64 s_lp[NB];
+  constexpr int NW = kPcThreads / 64;
+  __shared__ double w_sum[2][NW], w_max[2][NW];
+  __shared__ int w_idx[2][NW];
+  __shared__ z64 w_lp[2][NW][NB];
   if (stt->done) return;  // uniform: an earlier panel stopped
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int j0 = stt->r;
@@ -84,6 +87,7 @@ __global__ __launch_bounds__(kPcThreads) void k_pchol_panel(const z64* __restric
   double tres = 0.0;
 #pragma unroll
   for (int jj = 0; jj < NB; ++jj) {
+    const int b = jj & 1;
     // remaining trace and the pivot (largest remaining diagonal, lowest index on ties)
     double ls = 0.0, lm = -1.0;
     int li = INT_MAX;
@@ -108,44 +112,40 @@ __global__ __launch_bounds__(kPcThreads) void k_pchol_panel(const z64* __restric
         li = oi;
       }
     }
-    if (lane == 0) {
-      w_sum[w] = ls;
-      w_max[w] = lm;
-      w_idx[w] = li;
-    }
-    __syncthreads();
-    if (t == 0) {
-      double s = 0.0, bm = -1.0;
-      int bi = INT_MAX;
-      for (int k = 0; k < kPcThreads / 64; ++k) {
-        s += w_sum[k];
-        if (w_max[k] > bm || (w_max[k] == bm && w_idx[k] < bi)) {
-          bm = w_max[k];
-          bi = w_idx[k];
+    // the wave's candidate row (owned by a thread of this wave) posts its panel entries
+    if (li != INT_MAX && t == (li & (kPcThreads - 1))) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q)
+        if (q == li / kPcThreads) {
+#pragma unroll
+          for (int c = 0; c < jj; ++c) w_lp[b][w][c] = lp[q][c];
         }
-      }
-      b_sum = s;
-      b_max = bm;
-      b_idx = bi;
+    }
+    if (lane == 0) {
+      w_sum[b][w] = ls;
+      w_max[b][w] = lm;
+      w_idx[b][w] = li;
     }
     __syncthreads();
-    const double tot = b_sum, dp = b_max;
-    const int p = b_idx;
+    double tot = 0.0, dp = -1.0;
+    int p = INT_MAX, pw = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      tot += w_sum[b][k];
+      const double mk = w_max[b][k];
+      const int ik = w_idx[b][k];
+      if (mk > dp || (mk == dp && ik < p)) {
+        dp = mk;
+        p = ik;
+        pw = k;
+      }
+    }
     if (tot <= stop || !(dp > 0.0) || p >= m) {  // uniform across the workgroup
       tres = tot;
       stopped = true;
       break;
     }
-    // the pivot row's entries in this panel's earlier columns
-    if (t == p % kPcThreads) {
-#pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (q == p / kPcThreads) {
-#pragma unroll
-          for (int c = 0; c < jj; ++c) s_lp[c] = lp[q][c];
-        }
-    }
-    __syncthreads();
+    const z64* lpp = w_lp[b][pw];  // the pivot row's entries in this panel's earlier columns
     const double rp = sqrt(dp), irp = 1.0 / rp;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -161,9 +161,9 @@ __global__ __launch_bounds__(kPcThreads) void k_pchol_panel(const z64* __restric
           double sr = g.re, si = -g.im;
 #pragma unroll
           for (int c = 0; c < jj; ++c) {  // - L[i, c] conj(L[p, c])
-            const z64 a = lp[q][c], b = s_lp[c];
-            sr -= a.re * b.re + a.im * b.im;
-            si -= a.im * b.re - a.re * b.im;
+            const z64 a = lp[q][c], bb = lpp[c];
+            sr -= a.re * bb.re + a.im * bb.im;
+            si -= a.im * bb.re - a.re * bb.im;
           }
           l = z64{sr * irp, si * irp};
           dl[q] -= l.re * l.re + l.im * l.im;
@@ -173,7 +173,6 @@ __global__ __launch_bounds__(kPcThreads) void k_pchol_panel(const z64* __restric
       if (i < m) L[(size_t)i * ldl + j0 + jj] = l;
     }
     jdone = jj + 1;
-    __syncthreads();  // s_lp and the reduction slots are reused by the next step
   }
   // columns this panel did not produce are zero, so the host's update of the panel is exact
 #pragma unroll
