@@ -398,12 +398,13 @@ def main_grad(args):
     print(json.dumps(out), flush=True)
 
 
-def run_paper(g, name, n):
+def run_paper(g, name, n, layers=None):
     """One paper-workload circuit on the GPU with the bond-dimension criterion and the
-    exhaustive disentangler set; returns (seconds, gates, max bond after each T gate)."""
+    exhaustive disentangler set (N layers unless `layers` is given); returns (seconds, gates,
+    max bond after each T gate)."""
     import torch
     from paper_2511_06672_amd.workload import workload
-    wl = workload(name, n=n)
+    wl = workload(name, n=n, layers=layers)
     c = wl.circuit
     words = g.clifford_words(c.d, g.WORDS_DISENTANGLERS)
     st = g.State(g.make_config(c.d, c.n, wl.chi_max, wl.cutoff, criterion=g.CRITERION_BOND_DIM,
@@ -422,57 +423,82 @@ def run_paper(g, name, n):
     return time.perf_counter() - t0, c.n_phase_gates, dims
 
 
-def paper_cpu_baseline(runs):
-    """The oracle on the N = 12 paper circuits (same criterion and sets)."""
+def paper_cpu_baseline(runs, budget=None):
+    """The oracle on the N = 12 paper circuits (same criterion and sets).  With a budget (seconds
+    over all runs) no further gate starts once it is spent, so the last gate may overrun it."""
     import os
     from oracle.disentanglers import exhaustive_disentanglers
     from oracle.gcamps import Config, Gcamps
     from paper_2511_06672_amd.workload import Word, workload
-    gates, secs = 0, 0.0
-    for name, n in runs:
-        wl = workload(name, n=n)
+    gates, secs, parts = 0, 0.0, []
+    for name, n, layers in runs:
+        wl = workload(name, n=n, layers=layers)
         c = wl.circuit
         words = [Word(w, (0, 0, 0, 0)) for w in exhaustive_disentanglers(c.d)]
         t0 = time.perf_counter()
         orc = Gcamps(c.d, c.n, Config(chi_max=wl.chi_max, cutoff=wl.cutoff, criterion="bond_dim"), words)
+        done, spent = 0, False
         for layer in c.layers:
             for b in layer.bricks:
                 orc.apply_clifford(b.site, b.word.gens, b.word.weyl)
             for ph in layer.phases:
+                if budget is not None and secs + time.perf_counter() - t0 > budget:
+                    spent = True
+                    break
                 orc.apply_phase_rotation(ph.site, ph.phi)
+                done += 1
+            if spent:
+                break
         secs += time.perf_counter() - t0
-        gates += c.n_phase_gates
+        gates += done
+        tag = f"{name} n={n}" + (f" layers={layers}" if layers else "")
+        parts.append(f"{tag} {'first ' + str(done) + ' of ' + str(c.n_phase_gates) if spent else 'in full'}")
     return {"value": gates / secs, "unit": "non-Clifford gates/s", "cores": os.cpu_count() or 1,
-            "kind": "oracle", "sample": f"{', '.join(f'{a} n={b}' for a, b in runs)} in full "
-                                        f"({gates} gates, {secs:.1f} s)"}
+            "kind": "oracle", "sample": f"{', '.join(parts)} ({gates} gates, {secs:.1f} s)"}
 
 
 def main_paper(args):
     """The paper's own workload (random Clifford layers, T on qudit 0) with the bond-dimension
     criterion: qutrits and qubits at N = 12 and 16, N layers each (up to the transition, where
-    the bond dimension starts to grow)."""
+    the bond dimension starts to grow).  With --paper-layers F != 1: qutrits and qubits at
+    N = 12 for round(12 F) layers (F = 1.5 runs past the transition: qutrit bonds reach 729)."""
     import torch
     from paper_2511_06672_amd import gcamps as g
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    runs = [("paper_d3_n12", 12), ("paper_d2_n12", 12), ("paper_d3_n12", 16), ("paper_d2_n12", 16)]
+    f = args.paper_layers
+    if f == 1.0:
+        runs = [("paper_d3_n12", 12, None), ("paper_d2_n12", 12, None), ("paper_d3_n12", 16, None),
+                ("paper_d2_n12", 16, None)]
+    else:
+        nl = int(round(12 * f))
+        assert nl >= 1, "--paper-layers must give at least one layer at N = 12"
+        runs = [("paper_d3_n12", 12, nl), ("paper_d2_n12", 12, nl)]
     for w in range(args.warmup):
         log(f"warmup {w + 1}/{args.warmup}")
         run_paper(g, "paper_d3_n12", 8)
     per, gates, secs = {}, 0, 0.0
-    for name, n in runs:
-        t, ng, dims = run_paper(g, name, n)
-        log(f"{name} n={n}: {ng} T gates in {t:.2f} s, max bond per layer {dims}")
-        per[f"{name[:8]}_n{n}"] = {"seconds": t, "gates": ng, "gates_per_s": ng / t, "max_bond_per_layer": dims}
+    for name, n, layers in runs:
+        t, ng, dims = run_paper(g, name, n, layers)
+        log(f"{name} n={n} layers={layers or n}: {ng} T gates in {t:.2f} s, max bond per layer {dims}")
+        key = f"{name[:8]}_n{n}" + (f"_l{layers}" if layers else "")
+        per[key] = {"seconds": t, "gates": ng, "gates_per_s": ng / t, "max_bond_per_layer": dims}
         gates += ng
         secs += t
-    cpu = None if args.no_cpu else paper_cpu_baseline(runs[:2])
+    if args.no_cpu:
+        cpu = None
+    elif f == 1.0:
+        cpu = paper_cpu_baseline(runs[:2])
+    else:  # qubits first (cheap), then qutrit gates until the budget is spent
+        cpu = paper_cpu_baseline([runs[1], runs[0]], budget=args.cpu_budget)
     out = {
         "metric": "non-Clifford gates/sec, paper workload with the bond-dimension criterion",
         "value": gates / secs, "unit": "non-Clifford gates/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
         "ms_per_step": 1e3 * secs, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c128", "data": "synthetic (seeded random Clifford layers, T on qudit 0)",
-        "config": {"workload": "paper circuits: N in {12, 16}, N layers of (random Clifford, T on qudit 0), "
-                               "d in {2, 3}, exhaustive disentanglers, bond-dimension criterion, no truncation",
+        "config": {"workload": ("paper circuits: N in {12, 16}, N layers" if f == 1.0 else
+                                f"paper circuits: N = 12, {int(round(12 * f))} layers") +
+                               " of (random Clifford, T on qudit 0), d in {2, 3}, exhaustive disentanglers, "
+                               "bond-dimension criterion, no truncation",
                    "parallelism": "1 GPU"},
         "runs": per, "roofline": None, "cpu_baseline": cpu,
     }
@@ -667,6 +693,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--workload", choices=["headline", "batch", "grad", "paper", "gates", "mixed", "copy"], default="headline")
+    ap.add_argument("--paper-layers", type=float, default=1.0,
+                    help="paper: layers as a multiple of N (1: N = 12 and 16 up to the transition; "
+                         "otherwise N = 12 only, e.g. 1.5 runs past the transition)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--lanes", type=int, default=12,
                     help="batch: concurrent lanes (host threads with their own streams)")
