@@ -40,9 +40,10 @@ central differences of the frozen replay (h = 3e-5) over those angles, relative 
 
 A fourth runs the paper's own circuits (random Clifford layers, T on qudit 0; qutrits and
 qubits at N = 12 and 16, N layers) with the exhaustive disentanglers under the bond-dimension
-criterion, reporting the rate and the largest bond after each layer:
+criterion, reporting the rate and the largest bond after each layer.  --paper-layers 1.5 runs
+N = 12 for 18 layers instead, past the transition (qutrit bonds reach 729):
 
-    python bench.py --workload paper
+    python bench.py --workload paper [--paper-layers 1.5]
 
 A plain device copy of known size calibrates the HBM counters (FETCH_SIZE, WRITE_SIZE)
 used for the roofline's traffic figure:
