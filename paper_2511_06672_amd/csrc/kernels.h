@@ -32,7 +32,7 @@ struct EigWork {
   z64* V;      // block rotations
   int* flags;  // device flags
   int m_pad;
-  double* host_rb;  // pinned host read-back slots (2 doubles)
+  double* host_rb = nullptr;  // pinned host read-back slots (2 doubles); pageable locals when null
 };
 // Offsets in a context's pinned read-back block: device status, Cholesky state, eigensolver
 // slots, conjugated Weyl string and its error flag.
