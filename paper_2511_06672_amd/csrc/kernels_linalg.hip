@@ -1037,7 +1037,8 @@ __device__ void solve_pair(int k, const z64* __restrict__ Gs, int mp, int nb, in
 
 // One round of the block Jacobi sweep in one launch.  Blocks 0..half-1 (when step >= 0) solve the
 // sub-problems of outer step `step` (rotations to Vout, flags to pair_flag, any rotation to
-// *any_flag); when ps >= 0 the previous round (outer step ps, rotations Vp, flags pfp) is applied
+// *any_flag; a non-null any_next, the flag of the next sweep, is cleared); when ps >= 0 the previous
+// round (outer step ps, rotations Vp, flags pfp) is applied
 // beside them: the next half(half+1)/2 blocks form the tiles of Gd = V^H Gs V, the remaining
 // (mp/32) half blocks the row tiles of U <- U V.  The solves rebuild their sub-problems from Gs,
 // so no block waits for another; Gs and Gd alternate between rounds.  512 threads.
@@ -1052,7 +1053,8 @@ __global__ __launch_bounds__(512) void k_jround(const z64* __restrict__ Gs, z64*
                                                 const double* __restrict__ trace, double tol, double skip_rel,
                                                 int rel, double floor_rel, z64* __restrict__ Vout,
                                                 int* __restrict__ pair_flag, int* __restrict__ any_flag,
-                                                const z64* __restrict__ Vp, const int* __restrict__ pfp) {
+                                                int* __restrict__ any_next, const z64* __restrict__ Vp,
+                                                const int* __restrict__ pfp) {
   constexpr int PL = BJ2 * JLD;
   static_assert(6 * PL >= kRebuildLds, "the rebuild's scratch fits in the solve's planes");
   __shared__ double pool[6 * PL];
@@ -1061,6 +1063,7 @@ __global__ __launch_bounds__(512) void k_jround(const z64* __restrict__ Gs, z64*
   __shared__ int any, need;
   const int half = nb / 2, nsolve = step >= 0 ? half : 0, ngt = half * (half + 1) / 2;
   int b = blockIdx.x;
+  if (any_next && b == 0 && threadIdx.x == 0) *any_next = 0;
   if (b < nsolve) {
     // thresholds from the trace on the device (read by no host sync)
     const double tr = *trace;
@@ -1085,7 +1088,7 @@ __global__ void k_pad_copy(const z64* __restrict__ G, int m, int ldg, z64* __res
   Up[idx] = (i == j) ? z64{1.0, 0.0} : z64{0.0, 0.0};
 }
 
-__global__ void k_trace(const z64* __restrict__ Gp, int m, int mp, double* out) {
+__global__ void k_trace(const z64* __restrict__ Gp, int m, int mp, double* out, int* __restrict__ sweep_flags) {
   __shared__ double red[256];
   double s = 0.0;
   for (int i = threadIdx.x; i < m; i += blockDim.x) s += fabs(Gp[(size_t)i * mp + i].re);
@@ -1098,6 +1101,8 @@ __global__ void k_trace(const z64* __restrict__ Gp, int m, int mp, double* out) 
   if (threadIdx.x == 0) {
     out[0] = red[0];
     reinterpret_cast<int*>(out + 1)[0] = 0;  // pre-check flag, set by k_offdiag_check
+    sweep_flags[0] = 0;                      // the sweeps' rotation flags (even and odd sweeps)
+    sweep_flags[1] = 0;
   }
 }
 
@@ -1379,7 +1384,10 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks_for((size_t)mp * mp, 256)), dim3(256), 0, s, G, m, ldg, Gp, mp, Up);
   GC_LAUNCH_CHECK();
   double* d_trace = reinterpret_cast<double*>(w.flags + 512);
-  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, Gp, m, mp, d_trace);
+  // rotation flag of sweep sw: sweep_flag(sw); the first round of a sweep clears the next sweep's
+  // (written by no round of this sweep, and read by the host two sweeps ago), k_trace both
+  auto sweep_flag = [&](int sw) { return w.flags + 300 + (sw & 1); };
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, Gp, m, mp, d_trace, sweep_flag(0));
   GC_LAUNCH_CHECK();
   if (precheck) {
     hipLaunchKernelGGL(k_offdiag_check, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gp, m, mp, d_trace, tol,
@@ -1418,12 +1426,12 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   long round = 0;  // rounds launched so far
   int prev_step = -1;
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    GC_HIP(hipMemsetAsync(w.flags, 0, sizeof(int), s));
     for (int step = 0; step < nb - 1; ++step, ++round) {
       const bool upd = round > 0;
       hipLaunchKernelGGL(k_jround, dim3(half + (upd ? gtiles + utiles : 0)), dim3(kSolveThreads), pad, s,
                          upd ? gbuf(round - 1) : Gp, gbuf(round), Up, mp, nb, step, upd ? prev_step : -1, d_trace,
-                         tol, skip, rel, floor_rel, vbuf(round), fbuf(round), w.flags, upd ? vbuf(round - 1) : nullptr,
+                         tol, skip, rel, floor_rel, vbuf(round), fbuf(round), sweep_flag(sw),
+                         step == 0 ? sweep_flag(sw + 1) : nullptr, upd ? vbuf(round - 1) : nullptr,
                          upd ? fbuf(round - 1) : nullptr);
       GC_LAUNCH_CHECK();
       prev_step = step;
@@ -1433,7 +1441,7 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
     // convergence, costs as much here as that sweep: its rounds are cheap when nothing rotates.)
     int local = 0;
     int* hany = w.host_rb ? reinterpret_cast<int*>(w.host_rb) : &local;  // pinned when given
-    GC_HIP(hipMemcpyAsync(hany, w.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    GC_HIP(hipMemcpyAsync(hany, sweep_flag(sw), sizeof(int), hipMemcpyDeviceToHost, s));
     GC_HIP(hipStreamSynchronize(s));
     const int any = *hany;
     if (!any) {
@@ -1443,8 +1451,8 @@ void eig_hermitian(hipStream_t s, const z64* G, int m, int ldg, z64* U, int ldu,
   }
   // the last round's update: G into gbuf(round), U in place
   hipLaunchKernelGGL(k_jround, dim3(gtiles + utiles), dim3(kSolveThreads), pad, s, gbuf(round - 1), gbuf(round), Up, mp,
-                     nb, -1, prev_step, d_trace, tol, skip, rel, floor_rel, nullptr, nullptr, w.flags, vbuf(round - 1),
-                     fbuf(round - 1));
+                     nb, -1, prev_step, d_trace, tol, skip, rel, floor_rel, nullptr, nullptr, nullptr, nullptr,
+                     vbuf(round - 1), fbuf(round - 1));
   GC_LAUNCH_CHECK();
   const z64* Gf = gbuf(round);
   hipLaunchKernelGGL(k_unpad, dim3(blocks_for((size_t)m * m, 256)), dim3(256), 0, s, Gf, Up, m, mp, U, ldu, lam);
